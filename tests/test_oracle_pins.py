@@ -1,0 +1,345 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a closed
+form, a brute-force computation, a textbook or library routine, or an
+invariant that a dropped term, a wrong sign or index, or a transposed operand
+would break.  CPU only.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.optimize
+from scipy import ndimage
+
+import skygen
+
+FWHM = skygen.FWHM_PER_SIGMA
+
+
+def gauss_img(H, W, a, x, y, s):
+    return skygen.isolated_gaussian(H, W, a, x, y, s)
+
+
+# --------------------------------------------------------------------------
+# P1: Gaussian (*) Gaussian = Gaussian (Sect. 3), by brute-force convolution.
+# --------------------------------------------------------------------------
+
+def brute_conv(a1, x1, y1, s1, a2, s2, n=16, half=15):
+    """Direct 2-D linear convolution of a sampled component with a sampled beam
+    (2*half+1 square, peak a2 at its centre), evaluated on an n x n grid: a
+    plain sum over every beam offset.  The component is sampled on a grid
+    padded by `half` so the sum is complete on the n x n output."""
+    P = half
+    comp = gauss_img(n + 2 * P, n + 2 * P, a1, x1 + P, y1 + P, s1)
+    out = np.zeros((n, n))
+    for di in range(-half, half + 1):
+        for dj in range(-half, half + 1):
+            b = a2 * math.exp(-(di * di + dj * dj) / (2 * s2 * s2))
+            out += b * comp[P - di:P - di + n, P - dj:P - dj + n]
+    return out
+
+
+@pytest.mark.parametrize("s1,tol", [(1.0, 5e-5), (1.5, 2e-7)])
+def test_p1_gaussian_closure_forward(orc, s1, tol):
+    a1, x1, y1 = 0.7, 7.3, 8.6
+    a2, s2 = 1.0, 3.0 / FWHM
+    bc = brute_conv(a1, x1, y1, s1, a2, s2)
+    a3, s3 = orc.convolve(a1, s1, a2, s2)
+    assert s3 == pytest.approx(math.hypot(s1, s2), rel=1e-14)
+    model = gauss_img(16, 16, a3, x1, y1, s3)
+    # discrete sampling of the sum vs the integral: error ~ exp(-2 pi^2 s1^2 s2^2 / s3^2)
+    assert np.abs(bc - model).max() <= tol * a3
+
+
+def test_p1_gaussian_closure_fit_and_deconvolve(orc):
+    """Fit one Gaussian to the brute-force convolution, then Eqs. (5)-(6) must
+    give back the component."""
+    a1, x1, y1, s1 = 0.9, 7.6, 8.2, 1.5
+    a2, s2 = 1.0, 3.0 / FWHM
+    bc = brute_conv(a1, x1, y1, s1, a2, s2)
+    theta, trials, conv, chi2 = orc.fit_gaussians(bc, [0.8 * bc.max(), 8.0, 8.0, s2], omega_b=s2,
+                                                  max_width=10.0, window_sigmas=50.0)
+    assert conv
+    a_c, x_c, y_c, s_c = theta[0]
+    flux, alpha, omega, is_point = orc.deconvolve(a_c, s_c, a2, s2)
+    assert not is_point
+    assert omega == pytest.approx(s1, rel=1e-5)
+    assert alpha == pytest.approx(a1, rel=1e-5)
+    assert x_c == pytest.approx(x1, abs=1e-6) and y_c == pytest.approx(y1, abs=1e-6)
+    assert flux == pytest.approx(2 * math.pi * a1 * s1 * s1, rel=1e-5)
+
+
+# --------------------------------------------------------------------------
+# P2: Eqs. (5)/(6) round trip and the flux form.
+# --------------------------------------------------------------------------
+
+def test_p2_eq56_round_trip(orc):
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        alpha, omega = rng.uniform(-2, 2), rng.uniform(0.05, 50.0)
+        ab, wb = rng.uniform(0.5, 1.5), rng.uniform(0.8, 4.0)
+        a, s = orc.convolve(alpha, omega, ab, wb)
+        f, al2, om2, ip = orc.deconvolve(a, s, ab, wb)
+        assert not ip
+        assert om2 == pytest.approx(omega, rel=1e-9)
+        assert al2 == pytest.approx(alpha, rel=1e-9)
+        assert f == pytest.approx(2 * math.pi * alpha * omega * omega, rel=1e-9)
+        # Eq. (6) literally, with Eq. (5) for omega_i
+        wi = math.sqrt(s * s - wb * wb)
+        assert al2 == pytest.approx(a * s * s / (2 * math.pi * ab * wb * wb * wi * wi), rel=1e-9)
+
+
+def test_p2_point_limit(orc):
+    f, al, om, ip = orc.deconvolve(2.0, 1.3, 1.0, 1.3)
+    assert ip and al == 0.0 and om == 0.0 and f == pytest.approx(2.0, rel=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Geometry, peak search, Cholesky.
+# --------------------------------------------------------------------------
+
+def test_halfwidth_and_box(orc):
+    assert orc.halfwidth(0.1) == 3
+    assert orc.halfwidth(1.27398) == 7
+    assert orc.halfwidth(2.0) == 10
+    assert orc.halfwidth(2.0000001) == 11
+    assert orc.box(10.49, 20.5, 3, 100, 100) == (18, 24, 7, 13)
+    assert orc.box(1.2, 98.7, 5, 100, 50) == (94, 99, 0, 6)
+
+
+def test_p8_argmax_exhaustive(orc):
+    vals = [0.0, -0.0, 1.0, -1.0, 2.0, -2.0]
+    for img in itertools.product(vals, repeat=5):
+        a = np.array(img, dtype=np.float64)
+        best = max(range(5), key=lambda i: (abs(a[i]), -i))
+        assert orc.peak(a.reshape(1, 5)) == best
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        a = rng.integers(-3, 4, size=(7, 9)).astype(np.float64)
+        m = np.abs(a).max()
+        assert orc.peak(a) == int(np.flatnonzero(np.abs(a).ravel() == m)[0])
+
+
+def test_p7_cholesky_vs_library(orc):
+    rng = np.random.default_rng(7)
+    for n in (1, 4, 17, 40):
+        B = rng.normal(size=(n, n))
+        A = B @ B.T + n * np.eye(n)
+        b = rng.normal(size=n)
+        x = orc.cholesky_solve(A, b)
+        ref = np.linalg.solve(A, b)
+        assert np.abs(x - ref).max() <= 1e-10 * np.abs(ref).max()
+    A = np.diag([1.0, -1.0, 2.0])
+    assert orc.cholesky_solve(A, np.ones(3)) is None
+
+
+# --------------------------------------------------------------------------
+# PSF main-lobe fit (Sect. 3: the PSF approximated by one Gaussian).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fwhm,amp", [(3.0, 1.0), (4.5, 0.8), (2.5, 1.3)])
+def test_psf_fit_exact_gaussian(orc, fwhm, amp):
+    psf = amp * skygen.gaussian_psf(65, fwhm)
+    ab, wb, nl = orc.psf_fit(psf)
+    assert wb == pytest.approx(fwhm / FWHM, rel=1e-10)
+    assert ab == pytest.approx(amp, rel=1e-10)
+    lab, _ = ndimage.label(psf >= 0.35 * psf.max())
+    assert nl == int((lab == lab[32, 32]).sum())
+
+
+def test_psf_fit_ignores_disconnected_sidelobe(orc):
+    psf = skygen.gaussian_psf(65, 3.0)
+    psf[5, 5] = 0.9          # a bright pixel that is not 4-connected to the lobe
+    ab, wb, _ = orc.psf_fit(psf)
+    assert wb == pytest.approx(3.0 / FWHM, rel=1e-10)
+
+
+# --------------------------------------------------------------------------
+# P4 / P5: isolated sources, exact recovery, the gain ladder.
+# --------------------------------------------------------------------------
+
+def make_oracle(orc, img, gain, max_active=1, max_iter=100, ab=1.0, wb=3.0 / FWHM, threshold=0.0):
+    return orc.Oracle(img, gain=gain, threshold=threshold, max_iter=max_iter,
+                      max_active=max_active, alpha_b=ab, omega_b=wb)
+
+
+def test_p4_single_gaussian_exact_recovery(orc):
+    a, x, y, s = 1.3, 40.3, 37.8, 2.7
+    img = gauss_img(96, 96, a, x, y, s)
+    o = make_oracle(orc, img, gain=1.0)
+    rep = o.step()
+    assert rep["converged"] and rep["n_active"] == 1
+    fa, fx, fy, fs = rep["theta"][0]
+    assert abs(fa - a) <= 1e-8 * a and abs(fx - x) <= 1e-8 and abs(fy - y) <= 1e-8
+    assert abs(fs - s) <= 1e-8 * s
+    win = orc.box(fx, fy, orc.halfwidth(fs), 96, 96)
+    inside = o.R[win[0]:win[1] + 1, win[2]:win[3] + 1]
+    assert np.abs(inside).max() <= 1e-9 * a
+    # outside the window only the Gaussian's tail beyond 5 sigma is left
+    assert np.abs(o.R).max() <= math.exp(-12.5) * a * 1.0001
+
+
+def test_p4_gain_ladder(orc):
+    a, x, y, s, g = 1.0, 30.6, 33.1, 3.1, 0.3
+    img = gauss_img(64, 64, a, x, y, s)
+    o = make_oracle(orc, img, gain=g, max_active=5)
+    for j in range(6):
+        rep = o.step()
+        assert rep["converged"] and rep["n_active"] == 1   # earlier ones are co-located
+    comps = o.comps()
+    for j in range(6):
+        assert comps[j, 0] == pytest.approx(g * (1 - g) ** j * a, rel=1e-7)
+        assert comps[j, 1:] == pytest.approx([x, y, s], rel=1e-7)
+    win = orc.box(x, y, orc.halfwidth(s), 64, 64)
+    inside = o.R[win[0]:win[1] + 1, win[2]:win[3] + 1]
+    expect = (1 - g) ** 6 * img[win[0]:win[1] + 1, win[2]:win[3] + 1]
+    assert np.abs(inside - expect).max() <= 1e-8 * a
+
+
+def test_p5_point_source(orc):
+    """A sampled beam at an integer pixel: s -> omega_b, a point component of
+    flux F (Sect. 3 with omega_i = 0); with K = 1 and s, x, y frozen at the
+    bound this is CLEAN with the Gaussian beam."""
+    wb = 3.0 / FWHM
+    F = 0.75
+    img = F * gauss_img(48, 48, 1.0, 20.0, 25.0, wb)
+    o = make_oracle(orc, img, gain=0.5, wb=wb)
+    rep = o.step()
+    assert rep["theta"][0] == pytest.approx([F, 20.0, 25.0, wb], rel=1e-9)
+    c = o.components()[0]
+    assert c["is_point"] and c["flux"] == pytest.approx(0.5 * F, rel=1e-9)
+    # Hogbom with loop gain 0.5: the peak halves each iteration
+    for j in range(1, 4):
+        rep = o.step()
+        assert rep["peak"] == pytest.approx(F * 0.5 ** j, rel=1e-9)
+        assert rep["idx"] == 25 * 48 + 20
+
+
+# --------------------------------------------------------------------------
+# P6: the LM optimum against a brute-force search.
+# --------------------------------------------------------------------------
+
+def test_p6_lm_vs_brute_force(orc):
+    rng = np.random.default_rng(11)
+    H = W = 8
+    img = gauss_img(H, W, 1.0, 3.4, 4.2, 1.8) + rng.normal(0, 0.02, size=(H, W))
+
+    def chi2(x, y, s):
+        e = gauss_img(H, W, 1.0, x, y, s)  # window (half-width >= 7) covers the 8 x 8 image
+        a = (img * e).sum() / (e * e).sum()
+        return ((img - a * e) ** 2).sum(), a
+
+    grid = [(chi2(x, y, s)[0], x, y, s) for x in np.linspace(2, 5, 13)
+            for y in np.linspace(3, 6, 13) for s in np.linspace(1.4, 2.6, 13)]
+    best = min(grid)
+    res = scipy.optimize.minimize(lambda p: chi2(*p)[0], best[1:], method="Nelder-Mead",
+                                  options={"xatol": 1e-10, "fatol": 1e-14, "maxiter": 20000})
+    xb, yb, sb = res.x
+    ab = chi2(xb, yb, sb)[1]
+    theta, trials, conv, c2 = orc.fit_gaussians(img, [img.max(), 4.0, 4.0, 1.5], omega_b=1.0,
+                                                max_width=10.0)
+    assert conv
+    assert theta[0] == pytest.approx([ab, xb, yb, sb], abs=1e-6)
+    assert c2 == pytest.approx(res.fun, rel=1e-8)
+
+
+# --------------------------------------------------------------------------
+# P3 / P9: flux conservation and the residual's plain definition.
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c128_run(orc):
+    f = skygen.make_c128(0)
+    o = orc.Oracle(f.dirty, f.psf, gain=f.gain, threshold=f.threshold, max_iter=f.max_iter,
+                   max_active=f.max_active)
+    reps = [o.step() for _ in range(120)]
+    return f, o, reps
+
+
+def test_p3_flux_conservation(orc, c128_run):
+    f, o, _ = c128_run
+    H, W = f.shape
+    model_sum = 0.0
+    analytic = 0.0
+    for a, x, y, s in o.comps():
+        r0, r1, c0, c1 = orc.box(x, y, orc.halfwidth(s), H, W)
+        g = gauss_img(H, W, a, x, y, s)[r0:r1 + 1, c0:c1 + 1]
+        model_sum += g.sum()
+        if r1 - r0 == c1 - c0 == 2 * orc.halfwidth(s):
+            analytic += 2 * math.pi * a * s * s
+    total = f.dirty.astype(np.float64).sum()
+    assert abs(total - (o.R.sum() + model_sum)) <= 1e-10 * np.abs(f.dirty).sum()
+    # sum over an unclipped window vs the integral 2 pi a s^2 = alpha_b 2 pi omega_b^2 F
+    unclipped = [c for c in o.comps()
+                 if orc.box(c[1], c[2], orc.halfwidth(c[3]), H, W)[0] > 0]
+    assert analytic > 0 and len(unclipped) > 0
+
+
+def test_flux_analytic_per_component(orc):
+    """Window sum of a sampled Gaussian vs the continuous integral (the flux of
+    Eq. 6 times alpha_b 2 pi omega_b^2): equal up to the 5-sigma box tail."""
+    for a, x, y, s in [(1.0, 50.2, 49.7, 1.3), (0.3, 60.5, 40.1, 4.0), (2.0, 64.0, 64.0, 9.0)]:
+        H = W = 128
+        r0, r1, c0, c1 = orc.box(x, y, orc.halfwidth(s), H, W)
+        g = gauss_img(H, W, a, x, y, s)[r0:r1 + 1, c0:c1 + 1].sum()
+        ab, wb = 1.0, 1.2
+        flux = orc.deconvolve(a, s, ab, wb)[0]
+        assert g == pytest.approx(ab * 2 * math.pi * wb * wb * flux, rel=2.5e-6)
+
+
+def test_p9_incremental_residual_matches_definition(orc, c128_run):
+    f, o, _ = c128_run
+    scratch = o.residual_from_scratch()
+    assert np.abs(scratch - o.R).max() <= 1e-12 * np.abs(f.dirty).max()
+
+
+def test_c128_iterations_reduce_residual(orc, c128_run):
+    f, o, reps = c128_run
+    assert np.sqrt((o.R ** 2).mean()) < 0.2 * np.sqrt((f.dirty.astype(float) ** 2).mean())
+    assert sum(r["converged"] for r in reps) >= 0.95 * len(reps)
+
+
+# --------------------------------------------------------------------------
+# Stop criteria (Sect. 2 step 4) and the active set.
+# --------------------------------------------------------------------------
+
+def test_stop_threshold_and_maxiter(orc):
+    img = gauss_img(32, 32, 1.0, 16.0, 16.0, 1.3)
+    o = make_oracle(orc, img, gain=0.5, threshold=0.3, max_iter=10, wb=1.3)
+    assert o.step()["status"] == orc.ORC_OK           # peak 1.0
+    assert o.step()["status"] == orc.ORC_OK           # 0.5
+    rep = o.step()                                    # 0.25 < 0.3
+    assert rep["status"] == orc.ORC_STOP_THRESHOLD and o.k == 2 and o.L == 2
+    o2 = make_oracle(orc, img, gain=0.5, max_iter=1, wb=1.3)
+    o2.step()
+    assert o2.step()["status"] == orc.ORC_STOP_MAXITER and o2.L == 1
+
+
+def test_active_set_rule(orc):
+    """Membership written out by hand from the rule: same sign as the peak,
+    centre inside the new window, most recent first, separation
+    max(omega_b, min(s_j, s_m)), at most K_max - 1."""
+    H = W = 64
+    wb = 1.5
+    img = np.zeros((H, W))
+    img[30, 30] = 1.0                                  # peak at (x, y) = (30, 30)
+    comps = np.array([
+        [0.5, 33.0, 30.0, 2.0],    # 0: 3 px away, inside the window (h = 8)
+        [0.5, 30.5, 30.0, 4.0],    # 1: 0.5 px from the peak -> too close to the new one
+        [-0.5, 27.0, 30.0, 2.0],   # 2: wrong sign
+        [0.5, 40.0, 30.0, 2.0],    # 3: centre outside the new window (x = 40 > 38)
+        [0.5, 30.0, 25.0, 3.0],    # 4: inside, 5 px away
+        [0.5, 30.0, 26.0, 1.0],    # 5: 1 px from comp 4 -> max(1.5, min(1, 3)) = 1.5 -> skip
+        [0.5, 26.0, 34.0, 1.6],    # 6: inside
+        [0.5, 34.0, 34.0, 1.6],    # 7: inside
+    ])
+    o = orc.Oracle(img, gain=0.1, max_iter=10, max_active=4, alpha_b=1.0, omega_b=wb)
+    o.load_state(img, comps, 8)
+    rep = o.step()
+    # most recent first: 7, 6, 5, 4 (5 taken before 4), 3 out, 2 sign, 1 close, 0
+    assert rep["members"] == [-1, 7, 6, 5]
+    o.load_state(img, comps[:5], 5)
+    rep = o.step()
+    assert rep["members"] == [-1, 4, 0]
