@@ -1,0 +1,210 @@
+/*
+ * asp.h -- C ABI of the MI355X (gfx950) Asp-Clean2016 minor cycle.
+ *
+ * Method: L. Zhang, S. Bhatnagar, U. Rau, M. Zhang (2016), "Efficient
+ * implementation of the adaptive scale pixel decomposition algorithm".
+ * One minor-cycle iteration (the loop of Sect. 2, steps 1-4, with the fit of
+ * Sect. 3):
+ *   1. find the peak of |residual|                  (Sect. 2 step 1; Sect. 3,
+ *                                                      simple initial values)
+ *   2. stop on a threshold or an iteration count    (Sect. 2 step 4)
+ *   3. fit the active set of Gaussian components to the residual by
+ *      Levenberg-Marquardt; with the PSF taken as one Gaussian, each
+ *      component convolved with the PSF is an analytic Gaussian, so the
+ *      objective needs no convolution                (Sect. 3, Eq. 4)
+ *   4. scale the new component by the loop gain and subtract the fitted
+ *      Gaussians from the residual                   (Sect. 3; Sect. 2 step 3)
+ *   5. components are reported in the sky plane by analytic deconvolution of
+ *      the Gaussian beam                             (Sect. 3, Eqs. 5-6)
+ *
+ * Conventions
+ *   Images are FP32, row-major, H rows by W columns; pixel (r, c) is element
+ *   r*W + c; its centre is at x = c, y = r.  H*W must be below 2^32 - 1.
+ *   A Gaussian (a, x, y, s) is a * exp(-((c-x)^2 + (r-y)^2) / (2 s^2)),
+ *   point-sampled at pixel centres; s is the standard deviation.  "Convolved"
+ *   parameters are those of the fitted Gaussian (PSF (*) component); "sky"
+ *   parameters are the component's own (Eqs. 5-6).
+ * Ownership
+ *   The context owns all device memory it allocates.  Host arrays passed in
+ *   are copied and stay the caller's.  Device pointers passed to *_device
+ *   calls must stay valid only for the duration of the call.  Outputs go to
+ *   caller-provided buffers.
+ * Errors
+ *   Every call returns asp_status: negative values are errors (the context
+ *   keeps a message, see asp_last_error), positive values report a stop.
+ *   No C++ exception crosses this boundary.  A context is bound to one HIP
+ *   stream and is not thread-safe; distinct contexts are independent.
+ */
+#ifndef ASP_H
+#define ASP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASP_MAX_ACTIVE 16
+
+typedef struct asp_ctx asp_ctx;
+
+typedef enum {
+    ASP_OK = 0,
+    ASP_STOP_THRESHOLD = 1,      /* |peak| below the threshold (Sect. 2 step 4)  */
+    ASP_STOP_MAXITER = 2,        /* iteration count reached (Sect. 2 step 4)     */
+    ASP_LM_NOT_CONVERGED = 3,    /* the fit used its whole trial budget          */
+    ASP_ERR_INVALID_ARG = -1,
+    ASP_ERR_NONFINITE = -2,      /* NaN or Inf in an input image                 */
+    ASP_ERR_PSF = -3,            /* PSF peak not positive                        */
+    ASP_ERR_STATE = -4,          /* call out of order                            */
+    ASP_ERR_CAPACITY = -5,       /* component list or output buffer full         */
+    ASP_ERR_DEVICE = -6,         /* a HIP call failed                            */
+    ASP_ERR_NOMEM = -7
+} asp_status;
+
+/* A Gaussian in convolved (fit) space. */
+typedef struct { double amp, x, y, width; } asp_gauss;
+
+/* One component.  flux = 2 pi amp width^2 (sky plane); amp/width are alpha_i
+ * and omega_i of Eqs. 5-6; amp_c/width_c the fitted (convolved) amplitude
+ * and width after the loop gain; is_point = 1 when omega_i <= 1e-6 omega_b,
+ * then amp = 0 and flux carries the component. */
+typedef struct {
+    double flux, amp, x, y, width;
+    double amp_c, width_c;
+    int32_t is_point;
+    int32_t pad;
+    int64_t iter_added, iter_updated;
+} asp_component;
+
+/* Report of the last fit. members[0] = -1 is the new component, then the
+ * indices of the refitted old components. */
+typedef struct {
+    int32_t n_active;
+    int32_t members[ASP_MAX_ACTIVE];
+    int32_t lm_iters;            /* LM trials used (both fits if a fallback ran) */
+    int32_t converged;
+    int32_t used_fallback;       /* learned proposal failed; simple values used  */
+    int64_t idx;                 /* peak pixel                                   */
+    float peak;                  /* residual at the peak before the fit          */
+    float pad;
+    double chi2_init, chi2_final;/* sum over the fit's pixels of (D - M)^2       */
+    double theta0[4 * ASP_MAX_ACTIVE];   /* start (a, x, y, s) per member        */
+    double theta[4 * ASP_MAX_ACTIVE];    /* fitted, before the loop gain         */
+    int64_t fit_px;              /* pixels in the union of windows at the fit    */
+} asp_fit_report;
+
+typedef struct {
+    int32_t struct_size;         /* sizeof(asp_options)                          */
+    int32_t max_iter;            /* iteration count stop; default 1000           */
+    int32_t max_active;          /* K_max, 1..ASP_MAX_ACTIVE; default 5          */
+    int32_t lm_max_iter;         /* LM trial budget; default 100                 */
+    int32_t init_mode;           /* 0 simple initial values, 1 learned proposal  */
+    int32_t capacity;            /* component list size; 0 = max_iter            */
+    double window_sigmas;        /* window half-width factor c_w; default 5      */
+    double max_width;            /* upper bound on s; 0 = max(omega_b, min(H,W)/8) */
+    double lm_mu0;               /* initial damping; default 1e-3                */
+    double lm_tol;               /* step tolerance; default 1e-5                 */
+    double psf_lobe_frac;        /* main-lobe threshold; default 0.35            */
+    void *stream;                /* hipStream_t to run on; NULL = own stream     */
+} asp_options;
+
+typedef struct {
+    int64_t iterations;          /* iterations done by this call                 */
+    int64_t total_iterations;    /* k after the call                             */
+    int64_t components;          /* L after the call                             */
+    int64_t lm_trials;           /* trials summed over this call's fits          */
+    int64_t not_converged;       /* fits that used the whole budget              */
+    int64_t fallbacks;           /* learned proposals replaced by simple values  */
+} asp_run_report;
+
+/* Fill *opt with the defaults above. */
+asp_status asp_default_options(asp_options *opt);
+
+/*
+ * Create a context (Sect. 2, Eq. 1: dirty = PSF (*) sky + noise).
+ *   dirty  H x W host image; psf Hp x Wp host image with its peak anywhere.
+ *   gain   loop gain in (0, 1] (Sect. 3); threshold >= 0 (Sect. 2 step 4).
+ *   opt    NULL for defaults.
+ * Copies both images to the device, checks them for NaN/Inf
+ * (ASP_ERR_NONFINITE), fits the Gaussian main lobe of the PSF on the device
+ * (alpha_b, omega_b; Sect. 3) and allocates the component list.  On error
+ * *out is NULL.
+ */
+asp_status asp_create(const float *dirty, int64_t H, int64_t W,
+                      const float *psf, int64_t Hp, int64_t Wp,
+                      float gain, float threshold, const asp_options *opt, asp_ctx **out);
+
+/* As asp_create with device pointers (e.g. torch tensors); the images are
+ * copied device to device on the context's stream. */
+asp_status asp_create_device(const float *dirty_dev, int64_t H, int64_t W,
+                             const float *psf_dev, int64_t Hp, int64_t Wp,
+                             float gain, float threshold, const asp_options *opt,
+                             asp_ctx **out);
+
+void asp_destroy(asp_ctx *ctx);
+const char *asp_last_error(const asp_ctx *ctx);
+
+/*
+ * Step 1-2 (Sect. 2 steps 1 and 4): the peak of |residual|, the lowest
+ * row-major index winning ties, and the stop test.  Returns ASP_OK,
+ * ASP_STOP_THRESHOLD or ASP_STOP_MAXITER.  idx and value may be NULL.
+ */
+asp_status asp_find_peak(asp_ctx *ctx, int64_t *idx, float *value);
+
+/*
+ * Step 3 (Sect. 3, Eq. 4): select the active set around pixel idx and fit it
+ * by LM on the device.  init = NULL uses the simple initial values (the
+ * residual at idx and the main-lobe width); otherwise it is a proposal in
+ * convolved space (clamped to s >= omega_b and to 16 px of the peak), with
+ * the simple values as fallback if its fit does not converge.  Must follow
+ * asp_find_peak.  rep may be NULL.  Returns ASP_OK or ASP_LM_NOT_CONVERGED.
+ */
+asp_status asp_fit_active_set(asp_ctx *ctx, int64_t idx, const asp_gauss *init,
+                              asp_fit_report *rep);
+
+/*
+ * Step 4 (Sect. 3 loop gain; Sect. 2 step 3 with the Gaussian beam): commit
+ * the fit (new component with the loop gain, old members replaced by their
+ * refits) and update the residual on the windows involved.  Must follow
+ * asp_fit_active_set.  pixels_touched (nullable) receives the read-modify-
+ * written pixel count.
+ */
+asp_status asp_update_residual(asp_ctx *ctx, int64_t *pixels_touched);
+
+/* One full iteration (find_peak, fit, update) without host round trips. */
+asp_status asp_step(asp_ctx *ctx);
+
+/*
+ * Up to n_iter iterations on the device.  Iterations are queued in chunks
+ * with no host synchronisation inside a chunk; every kernel checks the
+ * device stop flag, so the run stops exactly where the stop test fires.
+ * Returns ASP_OK (n_iter done), ASP_STOP_THRESHOLD or ASP_STOP_MAXITER.
+ * rep may be NULL.
+ */
+asp_status asp_run(asp_ctx *ctx, int64_t n_iter, asp_run_report *rep);
+
+/*
+ * The component list with Eqs. 5-6 applied on the device.  Fills
+ * min(cap, L) entries; *n = L.  Returns ASP_ERR_CAPACITY if cap < L.
+ */
+asp_status asp_components(asp_ctx *ctx, asp_component *out, int64_t cap, int64_t *n);
+
+/* Raw convolved-space component list (a, x, y, s per row), FP64. */
+asp_status asp_components_raw(asp_ctx *ctx, double *out4, int64_t cap, int64_t *n);
+
+/* Copy the residual to a host buffer of H*W floats. */
+asp_status asp_residual(asp_ctx *ctx, float *out);
+/* Device pointer of the residual (valid until asp_destroy). */
+asp_status asp_residual_device(asp_ctx *ctx, float **dev);
+
+/* The Gaussian fitted to the PSF main lobe (Sect. 3: alpha_b, omega_b). */
+asp_status asp_psf_gauss(asp_ctx *ctx, double *alpha_b, double *omega_b);
+
+/* Iterations done (k) and components (L). */
+asp_status asp_counts(asp_ctx *ctx, int64_t *k, int64_t *L);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASP_H */

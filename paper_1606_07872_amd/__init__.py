@@ -1,0 +1,260 @@
+"""Python binding of the gfx950 Asp-Clean2016 minor cycle (``include/asp.h``).
+
+Argument marshalling only: every step of the minor cycle runs in the HIP
+kernels of ``libasp.so``.  Loading fails loudly when the library has not been
+built (``python -m paper_1606_07872_amd.build``); there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libasp.so")
+
+ASP_OK, ASP_STOP_THRESHOLD, ASP_STOP_MAXITER, ASP_LM_NOT_CONVERGED = 0, 1, 2, 3
+ASP_ERR_INVALID_ARG, ASP_ERR_NONFINITE, ASP_ERR_PSF, ASP_ERR_STATE = -1, -2, -3, -4
+ASP_ERR_CAPACITY, ASP_ERR_DEVICE, ASP_ERR_NOMEM = -5, -6, -7
+MAX_ACTIVE = 16
+
+# Every symbol include/asp.h declares.
+EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destroy",
+           "asp_last_error", "asp_find_peak", "asp_fit_active_set", "asp_update_residual",
+           "asp_step", "asp_run", "asp_components", "asp_components_raw", "asp_residual",
+           "asp_residual_device", "asp_psf_gauss", "asp_counts"]
+
+
+class AspError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"asp status {status}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("max_active", ctypes.c_int32), ("lm_max_iter", ctypes.c_int32),
+                ("init_mode", ctypes.c_int32), ("capacity", ctypes.c_int32),
+                ("window_sigmas", ctypes.c_double), ("max_width", ctypes.c_double),
+                ("lm_mu0", ctypes.c_double), ("lm_tol", ctypes.c_double),
+                ("psf_lobe_frac", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class Gauss(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double), ("x", ctypes.c_double), ("y", ctypes.c_double),
+                ("width", ctypes.c_double)]
+
+
+class Component(ctypes.Structure):
+    _fields_ = [("flux", ctypes.c_double), ("amp", ctypes.c_double), ("x", ctypes.c_double),
+                ("y", ctypes.c_double), ("width", ctypes.c_double), ("amp_c", ctypes.c_double),
+                ("width_c", ctypes.c_double), ("is_point", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("iter_added", ctypes.c_int64),
+                ("iter_updated", ctypes.c_int64)]
+
+
+class FitReport(ctypes.Structure):
+    _fields_ = [("n_active", ctypes.c_int32), ("members", ctypes.c_int32 * MAX_ACTIVE),
+                ("lm_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("used_fallback", ctypes.c_int32), ("idx", ctypes.c_int64),
+                ("peak", ctypes.c_float), ("pad", ctypes.c_float),
+                ("chi2_init", ctypes.c_double), ("chi2_final", ctypes.c_double),
+                ("theta0", ctypes.c_double * (4 * MAX_ACTIVE)),
+                ("theta", ctypes.c_double * (4 * MAX_ACTIVE)),
+                ("fit_px", ctypes.c_int64)]
+
+
+class RunReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("total_iterations", ctypes.c_int64),
+                ("components", ctypes.c_int64), ("lm_trials", ctypes.c_int64),
+                ("not_converged", ctypes.c_int64), ("fallbacks", ctypes.c_int64)]
+
+
+COMPONENT_DTYPE = np.dtype([("flux", "<f8"), ("amp", "<f8"), ("x", "<f8"), ("y", "<f8"),
+                            ("width", "<f8"), ("amp_c", "<f8"), ("width_c", "<f8"),
+                            ("is_point", "<i4"), ("pad", "<i4"), ("iter_added", "<i8"),
+                            ("iter_updated", "<i8")])
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run python -m paper_1606_07872_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, f32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+        P = ctypes.POINTER
+        L.asp_default_options.argtypes = [P(Options)]
+        L.asp_create.argtypes = [vp, i64, i64, vp, i64, i64, f32, f32, P(Options), P(vp)]
+        L.asp_create_device.argtypes = L.asp_create.argtypes
+        L.asp_destroy.argtypes = [vp]
+        L.asp_destroy.restype = None
+        L.asp_last_error.argtypes = [vp]
+        L.asp_last_error.restype = ctypes.c_char_p
+        L.asp_find_peak.argtypes = [vp, P(i64), P(f32)]
+        L.asp_fit_active_set.argtypes = [vp, i64, P(Gauss), P(FitReport)]
+        L.asp_update_residual.argtypes = [vp, P(i64)]
+        L.asp_step.argtypes = [vp]
+        L.asp_run.argtypes = [vp, i64, P(RunReport)]
+        L.asp_components.argtypes = [vp, vp, i64, P(i64)]
+        L.asp_components_raw.argtypes = [vp, vp, i64, P(i64)]
+        L.asp_residual.argtypes = [vp, vp]
+        L.asp_residual_device.argtypes = [vp, P(vp)]
+        L.asp_psf_gauss.argtypes = [vp, P(f64), P(f64)]
+        L.asp_counts.argtypes = [vp, P(i64), P(i64)]
+        for name in EXPORTS:
+            if name not in ("asp_destroy", "asp_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def default_options(**kw) -> Options:
+    opt = Options()
+    lib().asp_default_options(ctypes.byref(opt))
+    for k, v in kw.items():
+        if not hasattr(opt, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(opt, k, v)
+    return opt
+
+
+def _is_device_tensor(a) -> bool:
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+class Context:
+    """One deconvolution context (``asp_ctx``).  ``dirty`` and ``psf`` are
+    float32 host arrays (NumPy or CPU tensors), or float32 device tensors, in
+    which case ``asp_create_device`` copies them device to device."""
+
+    def __init__(self, dirty, psf, gain: float, threshold: float, **options):
+        self._ctx = ctypes.c_void_p()
+        opt = default_options(**options)
+        if _is_device_tensor(dirty):
+            if not _is_device_tensor(psf):
+                raise TypeError("dirty and psf must both be device tensors or both host arrays")
+            d, p = dirty.contiguous(), psf.contiguous()
+            if str(d.dtype) != "torch.float32" or str(p.dtype) != "torch.float32":
+                raise TypeError("float32 tensors required")
+            H, W = d.shape
+            Hp, Wp = p.shape
+            rc = lib().asp_create_device(d.data_ptr(), H, W, p.data_ptr(), Hp, Wp, gain,
+                                         threshold, ctypes.byref(opt), ctypes.byref(self._ctx))
+        else:
+            d = np.ascontiguousarray(np.asarray(dirty, dtype=np.float32))
+            p = np.ascontiguousarray(np.asarray(psf, dtype=np.float32))
+            H, W = d.shape
+            Hp, Wp = p.shape
+            rc = lib().asp_create(d.ctypes.data, H, W, p.ctypes.data, Hp, Wp, gain, threshold,
+                                  ctypes.byref(opt), ctypes.byref(self._ctx))
+        if rc != ASP_OK:
+            raise AspError(rc, "asp_create failed")
+        self.H, self.W = int(H), int(W)
+        self.options = opt
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if self._ctx:
+            lib().asp_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc):
+        """Negative statuses raise; stops (> 0) are returned."""
+        if rc < 0:
+            raise AspError(rc, lib().asp_last_error(self._ctx).decode())
+        return rc
+
+    # -- the step API ------------------------------------------------------
+    def find_peak(self):
+        idx, val = ctypes.c_int64(), ctypes.c_float()
+        rc = self._check(lib().asp_find_peak(self._ctx, ctypes.byref(idx), ctypes.byref(val)))
+        return rc, idx.value, val.value
+
+    def fit_active_set(self, idx: int, init=None):
+        rep = FitReport()
+        g = None
+        if init is not None:
+            g = Gauss(*[float(v) for v in init])
+        rc = self._check(lib().asp_fit_active_set(self._ctx, idx, ctypes.byref(g) if g else None,
+                                                   ctypes.byref(rep)))
+        return rc, report_dict(rep)
+
+    def update_residual(self) -> int:
+        n = ctypes.c_int64()
+        self._check(lib().asp_update_residual(self._ctx, ctypes.byref(n)))
+        return n.value
+
+    def step(self) -> int:
+        return self._check(lib().asp_step(self._ctx))
+
+    def run(self, n_iter: int):
+        rep = RunReport()
+        rc = self._check(lib().asp_run(self._ctx, n_iter, ctypes.byref(rep)))
+        return rc, {f: getattr(rep, f) for f, _ in RunReport._fields_}
+
+    # -- state -------------------------------------------------------------
+    def counts(self):
+        k, L = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().asp_counts(self._ctx, ctypes.byref(k), ctypes.byref(L)))
+        return k.value, L.value
+
+    def components(self) -> np.ndarray:
+        _, L = self.counts()
+        out = np.zeros(max(L, 1), dtype=COMPONENT_DTYPE)
+        n = ctypes.c_int64()
+        self._check(lib().asp_components(self._ctx, out.ctypes.data, L, ctypes.byref(n)))
+        return out[:L]
+
+    def components_raw(self) -> np.ndarray:
+        _, L = self.counts()
+        out = np.zeros((max(L, 1), 4), dtype=np.float64)
+        n = ctypes.c_int64()
+        self._check(lib().asp_components_raw(self._ctx, out.ctypes.data, L, ctypes.byref(n)))
+        return out[:L]
+
+    def residual(self) -> np.ndarray:
+        out = np.empty((self.H, self.W), dtype=np.float32)
+        self._check(lib().asp_residual(self._ctx, out.ctypes.data))
+        return out
+
+    def residual_device_ptr(self) -> int:
+        p = ctypes.c_void_p()
+        self._check(lib().asp_residual_device(self._ctx, ctypes.byref(p)))
+        return p.value
+
+    def psf_gauss(self):
+        a, w = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().asp_psf_gauss(self._ctx, ctypes.byref(a), ctypes.byref(w)))
+        return a.value, w.value
+
+
+def report_dict(rep: FitReport) -> dict:
+    m = rep.n_active
+    return {"n_active": m, "members": list(rep.members[:m]), "lm_iters": rep.lm_iters,
+            "converged": bool(rep.converged), "used_fallback": bool(rep.used_fallback),
+            "idx": rep.idx, "peak": rep.peak, "chi2_init": rep.chi2_init,
+            "chi2_final": rep.chi2_final,
+            "theta0": np.array(rep.theta0[: 4 * m]).reshape(-1, 4),
+            "theta": np.array(rep.theta[: 4 * m]).reshape(-1, 4), "fit_px": rep.fit_px}
+
+
+# The C names, for callers that prefer them.
+def asp_create(dirty, psf, gain, threshold, **options) -> Context:
+    return Context(dirty, psf, gain, threshold, **options)

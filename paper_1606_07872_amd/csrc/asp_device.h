@@ -1,0 +1,148 @@
+// Internal declarations of the gfx950 minor cycle: device state, launch
+// parameters, geometry helpers and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "asp.h"
+
+namespace asp {
+
+constexpr int kMaxM = ASP_MAX_ACTIVE;          // members of one fit
+constexpr int kMaxN = 4 * kMaxM;               // parameters of one fit
+constexpr int kMaxRects = 2 * (kMaxM - 1) + 1; // windows touched by one update
+constexpr int kFitThreads = 256;               // work-group of the fit kernel
+constexpr int kCols = kMaxN + 1;               // J columns + residual
+constexpr int kTileStride = kCols + 1;         // padded LDS row
+
+// A signed Gaussian on a window, one term of the residual update.
+struct Rect {
+    int32_t r0, r1, c0, c1;
+    double a, x, y, s;
+    float sign;
+    int32_t pad;
+};
+
+// Mutable per-context state in device memory.
+struct DevState {
+    unsigned long long peak_key;   // packed (|v| bits << 32) | (0xFFFFFFFF - idx)
+    int32_t stop;                  // 0 running, ASP_STOP_*, or ASP_ERR_CAPACITY
+    int32_t fit_ready;             // 1 between a fit and its residual update
+    int64_t k;                     // iterations done
+    int64_t L;                     // components
+    int64_t forced_idx;            // >= 0: fit this pixel instead of the peak key
+    int64_t idx;                   // pixel of the last fit
+    float peak;                    // residual there before the fit
+    int32_t have_proposal;         // 1: proposal[] holds a learned initial value
+    double proposal[4];
+    // report of the last fit
+    int32_t n_active, lm_iters, converged, used_fallback;
+    int32_t members[kMaxM];
+    double chi2_init, chi2_final;
+    double theta0[kMaxN], theta[kMaxN];
+    int64_t fit_px;
+    // update plan
+    int32_t n_rects, pad0;
+    Rect rects[kMaxRects];
+    int32_t bb[4];                 // bounding box of the rects
+    unsigned long long update_px;
+    // counters summed over iterations
+    unsigned long long sum_trials, not_converged, fallbacks;
+    // Gaussian main lobe of the PSF
+    double alpha_b, omega_b;
+    int64_t lobe_px;
+    int32_t psf_status, pad1;
+};
+
+// State of one fit shared by the work-groups of the fit kernel.  The
+// published part (m .. th_old) is written by one work-group and read by all
+// after the generation counter moves; the LM part is touched only by the
+// work-group that reduces a trial.
+constexpr int kNOutMax = (kMaxN + 1) * (kMaxN + 2) / 2;       // augmented Gram entries
+constexpr int kPartStride = kNOutMax + 3;                      // + F, chi2 (FP64), pixels
+
+struct FitGlobal {
+    int32_t m, n, done, phase;       // phase 0: start point under evaluation, 1: trial
+    double th_e[kMaxN];              // parameters under evaluation
+    double th_old[kMaxN];            // stored parameters of the old members
+    double th_c[kMaxN], g_c[kMaxN], lo[kMaxN], hi[kMaxN];
+    double th0[kMaxN];
+    double Hc[kMaxN * kMaxN];
+    double F_c, chi2_c, mu, nu, pred, chi2_init;
+    int32_t trials, trials_total, converged, used_fallback, use_prop, pass;
+    int32_t members[kMaxM];
+    int64_t idx, npx_c;
+    double peak;
+    unsigned int arrive, gen;
+    int32_t err, pad;
+};
+
+// Read-only launch parameters.
+struct Params {
+    float *R;                      // residual H x W
+    int64_t H, W;
+    double *ca, *cx, *cy, *cs;     // component list (SoA, FP64)
+    int64_t *c_added, *c_updated;
+    int64_t cap;
+    DevState *st;
+    double gain, threshold;
+    int64_t max_iter;
+    int32_t max_active, lm_max_iter;
+    double window_sigmas, max_width, lm_mu0, lm_tol;
+    int32_t use_proposal;          // honour st->proposal when have_proposal
+    int32_t fit_grid;              // work-groups of the fit kernel
+    FitGlobal *fg;
+    double *partials;              // fit_grid x kPartStride
+};
+
+// ---------------------------------------------------------------------------
+// Geometry (window rule of the fit and the update).  FP64 products and sums
+// are written so that no two roundings fuse into one.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline int halfwidth(double s, double window_sigmas)
+{
+    double h = ceil(window_sigmas * s);
+    if (!(h >= 3.0)) h = 3.0;
+    if (h > 1073741823.0) h = 1073741823.0;
+    return (int)h;
+}
+
+// Window of half-width h around (floor(x + 0.5), floor(y + 0.5)), clipped.
+__host__ __device__ inline void make_window(double x, double y, int h, int64_t H, int64_t W,
+                                            int32_t box[4])
+{
+    int64_t cx = (int64_t)floor(x + 0.5), cy = (int64_t)floor(y + 0.5);
+    int64_t r0 = cy - h, r1 = cy + h, c0 = cx - h, c1 = cx + h;
+    box[0] = (int32_t)(r0 < 0 ? 0 : r0);
+    box[1] = (int32_t)(r1 > H - 1 ? H - 1 : r1);
+    box[2] = (int32_t)(c0 < 0 ? 0 : c0);
+    box[3] = (int32_t)(c1 > W - 1 ? W - 1 : c1);
+}
+
+__host__ __device__ inline bool in_box(const int32_t b[4], int32_t r, int32_t c)
+{
+    return r >= b[0] && r <= b[1] && c >= b[2] && c <= b[3];
+}
+
+__device__ inline double width_cap(const Params &p)
+{
+    double m = p.max_width > 0.0 ? p.max_width
+                                 : (double)(p.H < p.W ? p.H : p.W) / 8.0;
+    return m > p.st->omega_b ? m : p.st->omega_b;
+}
+
+// Launchers (kernels.hip).
+hipError_t launch_peak(const Params &p, int grid, hipStream_t s);
+hipError_t launch_peak_decode(const Params &p, hipStream_t s);
+hipError_t launch_fit(const Params &p, hipStream_t s);
+hipError_t launch_update(const Params &p, int grid, hipStream_t s);
+hipError_t launch_psf_fit(const float *psf, int64_t Hp, int64_t Wp, double lobe_frac,
+                          DevState *st, int32_t *work, hipStream_t s);
+hipError_t launch_check_finite(const float *img, int64_t n, int32_t *flag, hipStream_t s);
+hipError_t launch_components(const Params &p, asp_component *out, hipStream_t s);
+hipError_t fit_kernel_setup();
+int fit_grid_size(int device);
+
+}  // namespace asp

@@ -1,0 +1,481 @@
+// Host runtime of the C ABI declared in include/asp.h: context lifetime,
+// argument checks, the step API and the device-resident run loop.  No C++
+// exception crosses the ABI; every HIP failure becomes ASP_ERR_DEVICE with a
+// message kept in the context.
+#include <math.h>
+#include <stddef.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "asp_device.h"
+
+using asp::DevState;
+using asp::Params;
+
+struct asp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t H = 0, W = 0, Hp = 0, Wp = 0;
+    asp_options opt{};
+    float *R = nullptr, *psf = nullptr;
+    double *ca = nullptr, *cx = nullptr, *cy = nullptr, *cs = nullptr;
+    int64_t *c_added = nullptr, *c_updated = nullptr;
+    int64_t cap = 0;
+    DevState *st = nullptr;
+    DevState *st_host = nullptr;          // pinned mirror for reads
+    int32_t *work = nullptr;
+    asp_component *comp_out = nullptr;
+    asp::FitGlobal *fg = nullptr;
+    double *partials = nullptr;
+    Params P{};
+    int peak_grid = 1024, update_grid = 1024;
+    int phase = 0;                        // 0 ready, 1 peak found, 2 fitted
+    std::string err;
+};
+
+namespace {
+
+asp_status fail(asp_ctx *c, asp_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_OR_FAIL(ctx, call)                                                         \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail((ctx), ASP_ERR_DEVICE,                                         \
+                        std::string(#call ": ") + hipGetErrorString(e_));             \
+    } while (0)
+
+template <typename T>
+hipError_t dev_alloc(T **p, size_t count)
+{
+    return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
+}
+
+void release(asp_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->R); (void)hipFree(c->psf);
+    (void)hipFree(c->ca); (void)hipFree(c->cx); (void)hipFree(c->cy); (void)hipFree(c->cs);
+    (void)hipFree(c->c_added); (void)hipFree(c->c_updated);
+    (void)hipFree(c->st); (void)hipFree(c->work); (void)hipFree(c->comp_out);
+    (void)hipFree(c->fg); (void)hipFree(c->partials);
+    if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+// Copy a field range of the device state to the pinned mirror and wait.
+asp_status pull_state(asp_ctx *c, size_t off, size_t len)
+{
+    HIP_OR_FAIL(c, hipMemcpyAsync((char *)c->st_host + off, (char *)c->st + off, len,
+                                  hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return ASP_OK;
+}
+
+asp_status pull_all(asp_ctx *c) { return pull_state(c, 0, sizeof(DevState)); }
+
+bool fit_setup_done = false;
+
+asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t W,
+                         const float *psf, bool psf_dev, int64_t Hp, int64_t Wp, float gain,
+                         float threshold, const asp_options *opt_in, asp_ctx **out)
+{
+    if (!out) return ASP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!dirty || !psf || H <= 0 || W <= 0 || Hp <= 0 || Wp <= 0) return ASP_ERR_INVALID_ARG;
+    if ((double)H * (double)W >= 4294967295.0) return ASP_ERR_INVALID_ARG;
+    if (!(gain > 0.0f && gain <= 1.0f) || !(threshold >= 0.0f) || !isfinite(threshold))
+        return ASP_ERR_INVALID_ARG;
+    asp_options opt;
+    asp_default_options(&opt);
+    if (opt_in) {
+        if (opt_in->struct_size != (int32_t)sizeof(asp_options)) return ASP_ERR_INVALID_ARG;
+        opt = *opt_in;
+    }
+    if (opt.max_iter < 0 || opt.max_active < 1 || opt.max_active > ASP_MAX_ACTIVE ||
+        opt.lm_max_iter < 1 || opt.init_mode < 0 || opt.init_mode > 1 || opt.capacity < 0 ||
+        !(opt.window_sigmas > 0.0) || !(opt.max_width >= 0.0) || !(opt.lm_mu0 > 0.0) ||
+        !(opt.lm_tol > 0.0) || !(opt.psf_lobe_frac > 0.0 && opt.psf_lobe_frac < 1.0))
+        return ASP_ERR_INVALID_ARG;
+
+    asp_ctx *c = new (std::nothrow) asp_ctx();
+    if (!c) return ASP_ERR_NOMEM;
+    c->H = H; c->W = W; c->Hp = Hp; c->Wp = Wp; c->opt = opt;
+    c->cap = opt.capacity > 0 ? opt.capacity : (opt.max_iter > 0 ? opt.max_iter : 1);
+    const int64_t n = H * W, np = Hp * Wp;
+    auto bail = [&](asp_status s) {
+        std::string msg = c->err;
+        release(c);
+        delete c;
+        fprintf(stderr, "asp_create: %s\n", msg.c_str());
+        return s;
+    };
+#define CREATE_HIP(call)                                                               \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            c->err = std::string(#call ": ") + hipGetErrorString(e_);                 \
+            return bail(e_ == hipErrorOutOfMemory ? ASP_ERR_NOMEM : ASP_ERR_DEVICE);  \
+        }                                                                              \
+    } while (0)
+
+    CREATE_HIP(hipGetDevice(&c->device));
+    if (opt.stream) {
+        c->stream = (hipStream_t)opt.stream;
+    } else {
+        CREATE_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    if (!fit_setup_done) {
+        CREATE_HIP(asp::fit_kernel_setup());
+        fit_setup_done = true;
+    }
+    CREATE_HIP(dev_alloc(&c->R, n));
+    CREATE_HIP(dev_alloc(&c->psf, np));
+    CREATE_HIP(dev_alloc(&c->ca, c->cap));
+    CREATE_HIP(dev_alloc(&c->cx, c->cap));
+    CREATE_HIP(dev_alloc(&c->cy, c->cap));
+    CREATE_HIP(dev_alloc(&c->cs, c->cap));
+    CREATE_HIP(dev_alloc(&c->c_added, c->cap));
+    CREATE_HIP(dev_alloc(&c->c_updated, c->cap));
+    CREATE_HIP(dev_alloc(&c->st, 1));
+    CREATE_HIP(dev_alloc(&c->work, np > 2 ? np : 2));
+    const int fit_grid = asp::fit_grid_size(c->device);
+    CREATE_HIP(dev_alloc(&c->fg, 1));
+    CREATE_HIP(dev_alloc(&c->partials, (size_t)fit_grid * asp::kPartStride));
+    CREATE_HIP(hipMemsetAsync(c->fg, 0, sizeof(asp::FitGlobal), c->stream));
+    CREATE_HIP(hipHostMalloc((void **)&c->st_host, sizeof(DevState), hipHostMallocDefault));
+
+    const hipMemcpyKind kd = dirty_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind kp = psf_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    CREATE_HIP(hipMemcpyAsync(c->R, dirty, sizeof(float) * n, kd, c->stream));
+    CREATE_HIP(hipMemcpyAsync(c->psf, psf, sizeof(float) * np, kp, c->stream));
+    memset(c->st_host, 0, sizeof(DevState));
+    c->st_host->forced_idx = -1;
+    CREATE_HIP(hipMemcpyAsync(c->st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice,
+                              c->stream));
+    // NaN / Inf in either image is an error (no CPU scan: a device kernel).
+    CREATE_HIP(hipMemsetAsync(c->work, 0, 2 * sizeof(int32_t), c->stream));
+    CREATE_HIP(asp::launch_check_finite(c->R, n, c->work, c->stream));
+    CREATE_HIP(asp::launch_check_finite(c->psf, np, c->work + 1, c->stream));
+    int32_t flags[2] = {0, 0};
+    CREATE_HIP(hipMemcpyAsync(flags, c->work, sizeof(flags), hipMemcpyDeviceToHost, c->stream));
+    CREATE_HIP(hipStreamSynchronize(c->stream));
+    if (flags[0] || flags[1]) {
+        c->err = flags[0] ? "dirty image holds NaN or Inf" : "PSF holds NaN or Inf";
+        return bail(ASP_ERR_NONFINITE);
+    }
+    CREATE_HIP(asp::launch_psf_fit(c->psf, Hp, Wp, opt.psf_lobe_frac, c->st, c->work, c->stream));
+    CREATE_HIP(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost,
+                              c->stream));
+    CREATE_HIP(hipStreamSynchronize(c->stream));
+    if (c->st_host->psf_status != 0 || !(c->st_host->omega_b > 0.0) ||
+        !isfinite(c->st_host->alpha_b)) {
+        c->err = "PSF peak is not positive or its main lobe cannot be fitted";
+        return bail(ASP_ERR_PSF);
+    }
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    const int64_t n4 = n / 4;
+    int64_t pg = cus * 8;
+    int64_t need = (n4 + 255) / 256;
+    c->peak_grid = (int)(need < pg ? (need > 0 ? need : 1) : pg);
+    c->update_grid = cus * 4;
+
+    Params &P = c->P;
+    P.R = c->R; P.H = H; P.W = W;
+    P.ca = c->ca; P.cx = c->cx; P.cy = c->cy; P.cs = c->cs;
+    P.c_added = c->c_added; P.c_updated = c->c_updated;
+    P.cap = c->cap;
+    P.st = c->st;
+    P.gain = (double)gain;
+    P.threshold = (double)threshold;
+    P.max_iter = opt.max_iter;
+    P.max_active = opt.max_active;
+    P.lm_max_iter = opt.lm_max_iter;
+    P.window_sigmas = opt.window_sigmas;
+    P.max_width = opt.max_width;
+    P.lm_mu0 = opt.lm_mu0;
+    P.lm_tol = opt.lm_tol;
+    P.use_proposal = 1;
+    P.fit_grid = fit_grid;
+    P.fg = c->fg;
+    P.partials = c->partials;
+    *out = c;
+    return ASP_OK;
+#undef CREATE_HIP
+}
+
+asp_status stop_status(const asp_ctx *c)
+{
+    int32_t s = c->st_host->stop;
+    if (s == ASP_STOP_THRESHOLD || s == ASP_STOP_MAXITER) return (asp_status)s;
+    if (s < 0) return (asp_status)s;
+    return ASP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+asp_status asp_default_options(asp_options *opt)
+{
+    if (!opt) return ASP_ERR_INVALID_ARG;
+    memset(opt, 0, sizeof *opt);
+    opt->struct_size = (int32_t)sizeof(asp_options);
+    opt->max_iter = 1000;
+    opt->max_active = 5;
+    opt->lm_max_iter = 100;
+    opt->init_mode = 0;
+    opt->capacity = 0;
+    opt->window_sigmas = 5.0;
+    opt->max_width = 0.0;
+    opt->lm_mu0 = 1e-3;
+    opt->lm_tol = 1e-5;
+    opt->psf_lobe_frac = 0.35;
+    opt->stream = nullptr;
+    return ASP_OK;
+}
+
+asp_status asp_create(const float *dirty, int64_t H, int64_t W, const float *psf, int64_t Hp,
+                      int64_t Wp, float gain, float threshold, const asp_options *opt,
+                      asp_ctx **out)
+{
+    return create_common(dirty, false, H, W, psf, false, Hp, Wp, gain, threshold, opt, out);
+}
+
+asp_status asp_create_device(const float *dirty_dev, int64_t H, int64_t W, const float *psf_dev,
+                             int64_t Hp, int64_t Wp, float gain, float threshold,
+                             const asp_options *opt, asp_ctx **out)
+{
+    return create_common(dirty_dev, true, H, W, psf_dev, true, Hp, Wp, gain, threshold, opt, out);
+}
+
+void asp_destroy(asp_ctx *ctx)
+{
+    release(ctx);
+    delete ctx;
+}
+
+const char *asp_last_error(const asp_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+asp_status asp_find_peak(asp_ctx *c, int64_t *idx, float *value)
+{
+    if (!c) return ASP_ERR_INVALID_ARG;
+    HIP_OR_FAIL(c, asp::launch_peak(c->P, c->peak_grid, c->stream));
+    HIP_OR_FAIL(c, asp::launch_peak_decode(c->P, c->stream));
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    if (idx) *idx = c->st_host->idx;
+    if (value) *value = c->st_host->peak;
+    s = stop_status(c);
+    c->phase = (s == ASP_OK) ? 1 : 0;
+    return s;
+}
+
+asp_status asp_fit_active_set(asp_ctx *c, int64_t idx, const asp_gauss *init,
+                              asp_fit_report *rep)
+{
+    if (!c) return ASP_ERR_INVALID_ARG;
+    if (c->phase != 1) return fail(c, ASP_ERR_STATE, "asp_fit_active_set needs asp_find_peak first");
+    if (idx < 0 || idx >= c->H * c->W) return fail(c, ASP_ERR_INVALID_ARG, "idx out of range");
+    DevState *h = c->st_host;
+    h->forced_idx = idx;
+    HIP_OR_FAIL(c, hipMemcpyAsync((char *)c->st + offsetof(DevState, forced_idx), &h->forced_idx,
+                                  sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    if (init) {
+        h->have_proposal = 1;
+        h->proposal[0] = init->amp; h->proposal[1] = init->x;
+        h->proposal[2] = init->y; h->proposal[3] = init->width;
+        HIP_OR_FAIL(c, hipMemcpyAsync((char *)c->st + offsetof(DevState, have_proposal),
+                                      &h->have_proposal,
+                                      offsetof(DevState, n_active) - offsetof(DevState, have_proposal),
+                                      hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_OR_FAIL(c, asp::launch_fit(c->P, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    asp_status st = stop_status(c);
+    if (st != ASP_OK) { c->phase = 0; return st; }
+    if (rep) {
+        memset(rep, 0, sizeof *rep);
+        rep->n_active = h->n_active;
+        for (int i = 0; i < h->n_active; ++i) rep->members[i] = h->members[i];
+        rep->lm_iters = h->lm_iters;
+        rep->converged = h->converged;
+        rep->used_fallback = h->used_fallback;
+        rep->idx = h->idx;
+        rep->peak = h->peak;
+        rep->chi2_init = h->chi2_init;
+        rep->chi2_final = h->chi2_final;
+        for (int i = 0; i < 4 * h->n_active; ++i) {
+            rep->theta0[i] = h->theta0[i];
+            rep->theta[i] = h->theta[i];
+        }
+        rep->fit_px = h->fit_px;
+    }
+    c->phase = 2;
+    return h->converged ? ASP_OK : ASP_LM_NOT_CONVERGED;
+}
+
+asp_status asp_update_residual(asp_ctx *c, int64_t *pixels_touched)
+{
+    if (!c) return ASP_ERR_INVALID_ARG;
+    if (c->phase != 2) return fail(c, ASP_ERR_STATE, "asp_update_residual needs a fit first");
+    HIP_OR_FAIL(c, asp::launch_update(c->P, c->update_grid, c->stream));
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    if (pixels_touched) *pixels_touched = (int64_t)c->st_host->update_px;
+    c->phase = 0;
+    return ASP_OK;
+}
+
+static asp_status enqueue_iteration(asp_ctx *c)
+{
+    HIP_OR_FAIL(c, asp::launch_peak(c->P, c->peak_grid, c->stream));
+    HIP_OR_FAIL(c, asp::launch_fit(c->P, c->stream));
+    HIP_OR_FAIL(c, asp::launch_update(c->P, c->update_grid, c->stream));
+    return ASP_OK;
+}
+
+asp_status asp_step(asp_ctx *c)
+{
+    if (!c) return ASP_ERR_INVALID_ARG;
+    if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_step inside a step-API sequence");
+    asp_status s = enqueue_iteration(c);
+    if (s != ASP_OK) return s;
+    s = pull_all(c);
+    if (s != ASP_OK) return s;
+    return stop_status(c);
+}
+
+asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
+{
+    if (!c || n_iter < 0) return ASP_ERR_INVALID_ARG;
+    if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_run inside a step-API sequence");
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    const int64_t k0 = c->st_host->k;
+    const unsigned long long t0 = c->st_host->sum_trials, nc0 = c->st_host->not_converged,
+                             fb0 = c->st_host->fallbacks;
+    int64_t done = 0;
+    asp_status result = stop_status(c);
+    while (result == ASP_OK && done < n_iter) {
+        const int64_t chunk = (n_iter - done) < 256 ? (n_iter - done) : 256;
+        for (int64_t i = 0; i < chunk; ++i) {
+            s = enqueue_iteration(c);
+            if (s != ASP_OK) return s;
+        }
+        s = pull_all(c);
+        if (s != ASP_OK) return s;
+        const int64_t before = done;
+        done = c->st_host->k - k0;
+        result = stop_status(c);
+        if (result == ASP_OK && done == before)
+            return fail(c, ASP_ERR_STATE, "no iteration progressed and no stop was set");
+    }
+    if (rep) {
+        rep->iterations = c->st_host->k - k0;
+        rep->total_iterations = c->st_host->k;
+        rep->components = c->st_host->L;
+        rep->lm_trials = (int64_t)(c->st_host->sum_trials - t0);
+        rep->not_converged = (int64_t)(c->st_host->not_converged - nc0);
+        rep->fallbacks = (int64_t)(c->st_host->fallbacks - fb0);
+    }
+    return result;
+}
+
+asp_status asp_components(asp_ctx *c, asp_component *out, int64_t cap, int64_t *n)
+{
+    if (!c || (!out && cap > 0) || cap < 0) return ASP_ERR_INVALID_ARG;
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    const int64_t L = c->st_host->L;
+    if (n) *n = L;
+    if (!c->comp_out) HIP_OR_FAIL(c, dev_alloc(&c->comp_out, c->cap));
+    const int64_t m = L < cap ? L : cap;
+    if (m > 0) {
+        HIP_OR_FAIL(c, asp::launch_components(c->P, c->comp_out, c->stream));
+        HIP_OR_FAIL(c, hipMemcpyAsync(out, c->comp_out, sizeof(asp_component) * m,
+                                      hipMemcpyDeviceToHost, c->stream));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    }
+    return cap < L ? ASP_ERR_CAPACITY : ASP_OK;
+}
+
+asp_status asp_components_raw(asp_ctx *c, double *out4, int64_t cap, int64_t *n)
+{
+    if (!c || (!out4 && cap > 0) || cap < 0) return ASP_ERR_INVALID_ARG;
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    const int64_t L = c->st_host->L;
+    if (n) *n = L;
+    const int64_t m = L < cap ? L : cap;
+    if (m > 0) {
+        double *tmp = nullptr;
+        HIP_OR_FAIL(c, hipHostMalloc((void **)&tmp, sizeof(double) * 4 * m, hipHostMallocDefault));
+        hipError_t e = hipSuccess;
+        double *src[4] = {c->ca, c->cx, c->cy, c->cs};
+        for (int f = 0; f < 4 && e == hipSuccess; ++f)
+            e = hipMemcpyAsync(tmp + f * m, src[f], sizeof(double) * m, hipMemcpyDeviceToHost,
+                               c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess)
+            for (int64_t j = 0; j < m; ++j)
+                for (int f = 0; f < 4; ++f) out4[4 * j + f] = tmp[f * m + j];
+        (void)hipHostFree(tmp);
+        if (e != hipSuccess) return fail(c, ASP_ERR_DEVICE, hipGetErrorString(e));
+    }
+    return cap < L ? ASP_ERR_CAPACITY : ASP_OK;
+}
+
+asp_status asp_residual(asp_ctx *c, float *out)
+{
+    if (!c || !out) return ASP_ERR_INVALID_ARG;
+    HIP_OR_FAIL(c, hipMemcpyAsync(out, c->R, sizeof(float) * c->H * c->W, hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return ASP_OK;
+}
+
+asp_status asp_residual_device(asp_ctx *c, float **dev)
+{
+    if (!c || !dev) return ASP_ERR_INVALID_ARG;
+    *dev = c->R;
+    return ASP_OK;
+}
+
+asp_status asp_psf_gauss(asp_ctx *c, double *alpha_b, double *omega_b)
+{
+    if (!c) return ASP_ERR_INVALID_ARG;
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    if (alpha_b) *alpha_b = c->st_host->alpha_b;
+    if (omega_b) *omega_b = c->st_host->omega_b;
+    return ASP_OK;
+}
+
+asp_status asp_counts(asp_ctx *c, int64_t *k, int64_t *L)
+{
+    if (!c) return ASP_ERR_INVALID_ARG;
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    if (k) *k = c->st_host->k;
+    if (L) *L = c->st_host->L;
+    return ASP_OK;
+}
+
+}  // extern "C"

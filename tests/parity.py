@@ -1,0 +1,74 @@
+"""Shared helpers of the GPU parity tests: the lockstep protocol.
+
+Lockstep: the GPU advances one iteration; the oracle is loaded with the GPU's
+pre-step state (residual converted exactly from FP32 to FP64, the FP64
+component list, the iteration count, the GPU's alpha_b/omega_b) and steps
+once.  Then:
+  * the peak index and the active-set members (in order) must be equal,
+  * every member's a and s must agree to 1e-3 relative and x, y to
+    1e-3 * max(1, s) pixels,
+  * the residuals must agree to 1e-4 * max|dirty|.
+"""
+import numpy as np
+
+import oracle
+
+PARAM_RTOL = 1e-3
+RESID_TOL = 1e-4
+
+
+def param_errors(gpu_theta, orc_theta):
+    """Per-member error ratios (value / allowed) for a, x, y, s."""
+    g = np.asarray(gpu_theta, dtype=np.float64).reshape(-1, 4)
+    o = np.asarray(orc_theta, dtype=np.float64).reshape(-1, 4)
+    out = []
+    for (ga, gx, gy, gs), (oa, ox, oy, os_) in zip(g, o):
+        ra = abs(ga - oa) / (PARAM_RTOL * max(abs(oa), 1e-30))
+        rs = abs(gs - os_) / (PARAM_RTOL * os_)
+        pos = PARAM_RTOL * max(1.0, os_)
+        out.append((ra, abs(gx - ox) / pos, abs(gy - oy) / pos, rs))
+    return np.array(out)
+
+
+class Lockstep:
+    def __init__(self, ctx, field, **orc_kw):
+        self.ctx = ctx
+        self.f = field
+        ab, wb = ctx.psf_gauss()
+        self.orc = oracle.Oracle(field.dirty, gain=field.gain, threshold=field.threshold,
+                                 max_iter=field.max_iter, max_active=field.max_active,
+                                 alpha_b=ab, omega_b=wb, cap=field.max_iter + 1, **orc_kw)
+        self.peak = float(np.abs(field.dirty).max())
+        self.records = []
+
+    def step(self, init=None):
+        ctx, orc = self.ctx, self.orc
+        R0 = ctx.residual()
+        comps0 = ctx.components_raw()
+        k0, _ = ctx.counts()
+        rc, idx, val = ctx.find_peak()
+        orc.load_state(R0, comps0, k0)
+        orep = orc.step(init=init)
+        if rc != 0:
+            assert orep["status"] == rc, (rc, orep["status"])
+            return None
+        rc, rep = ctx.fit_active_set(idx, init=init)
+        ctx.update_residual()
+        R1 = ctx.residual().astype(np.float64)
+        rec = {"k": k0, "idx": idx, "orc_idx": orep["idx"], "members": rep["members"],
+               "orc_members": orep["members"], "gpu_conv": rep["converged"],
+               "orc_conv": orep["converged"], "gpu_theta": rep["theta"],
+               "orc_theta": orep["theta"], "resid_err": float(np.abs(R1 - orc.R).max()),
+               "gpu_trials": rep["lm_iters"], "orc_trials": orep["lm_iters"]}
+        if rec["members"] == rec["orc_members"]:
+            rec["param_err"] = param_errors(rep["theta"], orep["theta"])
+        self.records.append(rec)
+        return rec
+
+    def check(self, rec, strict=True):
+        assert rec["idx"] == rec["orc_idx"], rec
+        assert rec["members"] == rec["orc_members"], rec
+        assert rec["resid_err"] <= RESID_TOL * self.peak, (rec["resid_err"], rec["k"])
+        if strict:
+            assert rec["param_err"].max() <= 1.0, (rec["k"], rec["param_err"], rec["gpu_theta"],
+                                                   rec["orc_theta"])
