@@ -70,6 +70,7 @@ def main():
     value = done / secs if secs > 0 else 0.0
     print(f"[bench] {done} iterations in {secs:.3f}s, trials {rep['lm_trials']}, "
           f"not converged {rep['not_converged']}", file=sys.stderr, flush=True)
+    print(f"[bench] fit profile {ctx.fit_profile()}", file=sys.stderr, flush=True)
     line = {
         "metric": "minor-cycle iterations/s",
         "value": value,

@@ -204,6 +204,12 @@ asp_status asp_psf_gauss(asp_ctx *ctx, double *alpha_b, double *omega_b);
 /* Iterations done (k) and components (L). */
 asp_status asp_counts(asp_ctx *ctx, int64_t *k, int64_t *L);
 
+/* Diagnostics: accumulated fit-kernel phase timers in microseconds and event
+ * counts, n <= 10 entries: check-in, setup, evaluation (one work-group),
+ * waits (one work-group), reduction, LM step, commit, trials, fits, pixels
+ * evaluated.  Reading does not reset them. */
+asp_status asp_fit_profile(asp_ctx *ctx, double *out, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

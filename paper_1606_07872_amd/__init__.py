@@ -23,7 +23,7 @@ MAX_ACTIVE = 16
 EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destroy",
            "asp_last_error", "asp_find_peak", "asp_fit_active_set", "asp_update_residual",
            "asp_step", "asp_run", "asp_components", "asp_components_raw", "asp_residual",
-           "asp_residual_device", "asp_psf_gauss", "asp_counts"]
+           "asp_residual_device", "asp_psf_gauss", "asp_counts", "asp_fit_profile"]
 
 
 class AspError(RuntimeError):
@@ -106,6 +106,7 @@ def lib():
         L.asp_residual_device.argtypes = [vp, P(vp)]
         L.asp_psf_gauss.argtypes = [vp, P(f64), P(f64)]
         L.asp_counts.argtypes = [vp, P(i64), P(i64)]
+        L.asp_fit_profile.argtypes = [vp, vp, ctypes.c_int32]
         for name in EXPORTS:
             if name not in ("asp_destroy", "asp_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -238,6 +239,14 @@ class Context:
         p = ctypes.c_void_p()
         self._check(lib().asp_residual_device(self._ctx, ctypes.byref(p)))
         return p.value
+
+    PROFILE_FIELDS = ("checkin_us", "setup_us", "eval_us", "wait_us", "reduce_us", "lmstep_us",
+                      "commit_us", "trials", "fits", "eval_px")
+
+    def fit_profile(self) -> dict:
+        out = np.zeros(len(self.PROFILE_FIELDS))
+        self._check(lib().asp_fit_profile(self._ctx, out.ctypes.data, len(out)))
+        return dict(zip(self.PROFILE_FIELDS, out.tolist()))
 
     def psf_gauss(self):
         a, w = ctypes.c_double(), ctypes.c_double()

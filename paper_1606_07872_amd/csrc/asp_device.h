@@ -24,6 +24,8 @@ struct Rect {
     int32_t pad;
 };
 
+constexpr int kProfSlots = 10;
+
 // Mutable per-context state in device memory.
 struct DevState {
     unsigned long long peak_key;   // packed (|v| bits << 32) | (0xFFFFFFFF - idx)
@@ -53,6 +55,8 @@ struct DevState {
     double alpha_b, omega_b;
     int64_t lobe_px;
     int32_t psf_status, pad1;
+    // fit phase timers (device wall clock ticks) and event counts
+    unsigned long long prof[kProfSlots];
 };
 
 // State of one fit shared by the work-groups of the fit kernel.  The
@@ -61,21 +65,15 @@ struct DevState {
 // work-group that reduces a trial.
 constexpr int kNOutMax = (kMaxN + 1) * (kMaxN + 2) / 2;       // augmented Gram entries
 constexpr int kPartStride = kNOutMax + 3;                      // + F, chi2 (FP64), pixels
+constexpr int kMaxGroups = 64;     // partial rows beyond the grid, one per arrival group
 
 struct FitGlobal {
-    int32_t m, n, done, phase;       // phase 0: start point under evaluation, 1: trial
-    double th_e[kMaxN];              // parameters under evaluation
-    double th_old[kMaxN];            // stored parameters of the old members
-    double th_c[kMaxN], g_c[kMaxN], lo[kMaxN], hi[kMaxN];
-    double th0[kMaxN];
-    double Hc[kMaxN * kMaxN];
-    double F_c, chi2_c, mu, nu, pred, chi2_init;
-    int32_t trials, trials_total, converged, used_fallback, use_prop, pass;
-    int32_t members[kMaxM];
-    int64_t idx, npx_c;
-    double peak;
-    unsigned int arrive, gen;
-    int32_t err, pad;
+    int32_t m, n, done, pad0;
+    double th_e[kMaxN];                 // parameters under evaluation
+    double th_old[kMaxN];               // stored parameters of the old members
+    unsigned int gen;                   // publication counter
+    unsigned int top;                   // second-level arrivals (one per group)
+    unsigned int arrive_g[kMaxGroups];  // first-level arrivals (one per work-group)
 };
 
 // Read-only launch parameters.

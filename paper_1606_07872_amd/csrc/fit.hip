@@ -2,28 +2,27 @@
 // (Zhang, Bhatnagar, Rau & Zhang 2016, Sect. 3, Eq. 4) spread over the whole
 // GPU.
 //
-// One cooperative launch, one work-group per CU.  Work-group 0 takes the
-// peak, applies the stop test (Sect. 2 step 4), forms the start values (the
-// simple initial values of Sect. 3, or a clamped proposal) and selects the
-// active set.  Every LM trial then evaluates
+// One cooperative launch, one work-group per CU.  Work-group 0 owns the fit:
+// it takes the peak, applies the stop test (Sect. 2 step 4), forms the start
+// values (the simple initial values of Sect. 3, or a clamped proposal),
+// selects the active set, keeps the LM state in its LDS, and after every
+// trial reduces, solves and publishes the next trial point.  Every LM trial
+// evaluates
 //     F(theta) = sum_{U(theta)} M (M - 2 D),   H = J^T J,   g = J^T (D - M)
 // over U(theta), the union of the members' windows at theta (a truncated
-// Gaussian is zero outside its window, so this is the whole-image objective
-// of Eq. 4 up to a constant).  D is the residual with the old members'
-// stored Gaussians added back.  The 256-pixel tiles of U are dealt to the
-// work-groups.  Per pixel, D, M, the residual r = D - M and the objective
-// term M (M - 2D) are formed in FP64 (r is a small difference of O(1) terms);
-// J (from the same values) and r go to FP32 for the augmented Gram matrix
-// [J r]^T [J r], accumulated with Kahan compensation, while F and chi2 are
-// accumulated in FP64.  Each work-group writes an FP64 partial; the last
-// work-group to arrive sums the partials in
-// work-group order, solves the damped normal equations by Cholesky in FP64,
-// runs the LM bookkeeping and publishes the next trial point.  The work-group
-// that finishes the fit commits it (loop gain on the new component, refits
-// replace the old members) and writes the residual-update plan.
+// Gaussian is zero outside its window, so F is the whole-image objective of
+// Eq. 4 up to a constant); D is the residual with the old members' stored
+// Gaussians added back.  The 256-pixel tiles of U are dealt to the first
+// geff work-groups.  Per pixel, D, M, the residual r = D - M and M (M - 2 D)
+// are formed in FP64 (r is a small difference of O(1) terms); J and r go to
+// FP32 for the augmented Gram matrix [J r]^T [J r], summed per tile and
+// Kahan-compensated across tiles, while F and chi2 stay FP64.
 //
-// Every wait is bounded; a wait that runs out marks the context with
-// ASP_ERR_DEVICE and every work-group leaves.
+// Every work-group arrives once per round: at its group's counter (kGroup
+// work-groups), the last of a group sums the group's partial rows in order and
+// arrives at the top counter; work-group 0 waits for all groups, so no
+// work-group can fall a round behind.  Every wait is bounded; a wait that runs
+// out marks the context with ASP_ERR_DEVICE and every work-group leaves.
 #include <math.h>
 
 #include "asp_device.h"
@@ -32,57 +31,94 @@ namespace asp {
 
 constexpr int kT = kFitThreads;
 constexpr int kOwnMax = (kNOutMax + kT - 1) / kT;
-constexpr size_t kFitLds =
-    sizeof(float) * kT * kTileStride + sizeof(double) * (2 * kMaxN * kMaxN + kT);
+constexpr size_t kTileBytes = sizeof(float) * kT * kTileStride;
+constexpr size_t kMatBytes = sizeof(double) * kMaxN * kMaxN;
+constexpr size_t kFitLds = kTileBytes + 2 * kMatBytes;   // tile (or A) | He | Hc
 constexpr long kSpinLimit = 1L << 22;
+constexpr int kMinTiles = 2;      // least tiles per evaluating work-group
+constexpr int kSoloTiles = 96;    // trials up to this many tiles: work-group 0 alone
+constexpr int kGroup = 16;        // work-groups per first-level arrival group
+static_assert(kTileBytes >= kMatBytes, "A shares the tile buffer");
+
+// Phase timer slots of DevState::prof.
+enum { kPCheckin = 0, kPSetup, kPEval, kPWait, kPReduce, kPLmStep, kPCommit, kPTrials, kPFits,
+       kPEvalPx };
+
+__device__ inline unsigned long long now_ticks() { return wall_clock64(); }
 
 struct WGShared {
+    // member constants at the parameters under evaluation
     int32_t win[kMaxM][4], wold[kMaxM][4];
     int64_t pref[kMaxM + 1];
     double mx[kMaxM], my[kMaxM], mamp[kMaxM], minv2[kMaxM], minvs2[kMaxM], minvs3[kMaxM];
     double ox[kMaxM], oy[kMaxM], oamp[kMaxM], oinv2[kMaxM];
     int32_t m, n;
+    double wsum[4][3];
+    double wred[kT / 64][48];
+    // the reduced trial (work-group 0)
     double ge[kMaxN], Fe, chi2e;
     int64_t npx_e;
-    double dd[kMaxN], rhs[kMaxN], rhs_copy[kMaxN], delta[kMaxN], th_t[kMaxN];
+    // LM state (work-group 0)
+    double th_c[kMaxN], th_e[kMaxN], g_c[kMaxN], lo[kMaxN], hi[kMaxN], th0[kMaxN], th_old[kMaxN];
+    double dd[kMaxN], rhs[kMaxN], rhs_copy[kMaxN], delta[kMaxN];
     int32_t frozen[kMaxN];
+    double F_c, chi2_c, mu, nu, pred, chi2_init, peak;
+    int32_t trials, trials_total, converged, used_fallback, use_prop, pass, phase;
+    int32_t members[kMaxM];
+    int64_t idx, npx_c;
+    // selection scratch
     uint32_t mask[kT];
     double t0[4];
-    int32_t members[kMaxM];
     int32_t nch, sel_done;
+    // control
     unsigned int gen;
     int32_t last, abort, done, ok, finished, accept, stop;
 };
 
 // ---------------------------------------------------------------------------
-// Synchronisation between work-groups.
+// Synchronisation between work-groups.  Polling is relaxed (no cache
+// maintenance per poll); the fence after it is the acquire.  Before a
+// work-group signals, every thread issues a release fence for its own stores.
 // ---------------------------------------------------------------------------
 
 __device__ bool wait_publish(FitGlobal *G, WGShared &S)
 {
     if (threadIdx.x == 0) {
         unsigned int now = S.gen;
-        // relaxed polling (no cache invalidation per poll); the fence below
-        // is the acquire
         for (long it = 0; it < kSpinLimit; ++it) {
             now = __hip_atomic_load(&G->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (now != S.gen) break;
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
         }
         S.abort = (now == S.gen) ? 1 : 0;
         S.gen = now;
+        __threadfence();
     }
     __syncthreads();
-    __threadfence();
     return S.abort == 0;
 }
 
+__device__ inline void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+
 __device__ void publish(FitGlobal *G)
 {
-    __threadfence();
+    release_fence();
     __syncthreads();
     if (threadIdx.x == 0)
         __hip_atomic_fetch_add(&G->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits until *ctr reaches target; returns false on timeout.
+__device__ bool spin_until(unsigned int *ctr, unsigned int target)
+{
+    long it = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
+           it < kSpinLimit) {
+        __builtin_amdgcn_s_sleep(1);
+        ++it;
+    }
+    __threadfence();
+    return it < kSpinLimit;
 }
 
 // ---------------------------------------------------------------------------
@@ -103,15 +139,29 @@ __device__ inline bool too_close(double xj, double yj, double sj, double xm, dou
     return __dadd_rn(__dmul_rn(ex, ex), __dmul_rn(ey, ey)) <= __dmul_rn(rs, rs);
 }
 
-// Start values into S.t0 (thread 0), then the active set, the bounds and the
-// published start point.  Whole work-group.
+// Lane 0 of wave 0: greedy acceptance of candidate j.
+__device__ inline void consider(const Params &p, WGShared &S, int64_t j, double omega_b)
+{
+    const double xj = p.cx[j], yj = p.cy[j], sj = p.cs[j];
+    if (too_close(xj, yj, sj, S.t0[1], S.t0[2], S.t0[3], omega_b)) return;
+    for (int u = 0; u < S.nch; ++u) {
+        const int64_t mj = S.members[u + 1];
+        if (too_close(xj, yj, sj, p.cx[mj], p.cy[mj], p.cs[mj], omega_b)) return;
+    }
+    S.members[1 + S.nch] = (int32_t)j;
+    S.nch++;
+    if (S.nch >= p.max_active - 1) S.sel_done = 1;
+}
+
+// Start values, active set, bounds; the start point goes to S.th_e and is
+// published in G.  Work-group 0, whole work-group.
 __device__ void setup_fit(const Params &p, FitGlobal *G, WGShared &S, bool use_prop)
 {
     const int t = threadIdx.x;
     const double omega_b = p.st->omega_b;
     if (t == 0) {
-        const int64_t pr = G->idx / p.W, pc = G->idx % p.W;
-        const double pv = G->peak;
+        const int64_t pr = S.idx / p.W, pc = S.idx % p.W;
+        const double pv = S.peak;
         double *t0 = S.t0;
         const double cap = width_cap(p);
         if (use_prop) {
@@ -136,7 +186,7 @@ __device__ void setup_fit(const Params &p, FitGlobal *G, WGShared &S, bool use_p
         S.sel_done = (p.max_active <= 1) ? 1 : 0;
     }
     __syncthreads();
-    const double a0 = S.t0[0], x0 = S.t0[1], y0 = S.t0[2], s0 = S.t0[3];
+    const double a0 = S.t0[0];
     const int32_t b0 = S.win[0][0], b1 = S.win[0][1], b2 = S.win[0][2], b3 = S.win[0][3];
     const int64_t L = p.st->L;
     constexpr int64_t kSeg = (int64_t)kT * 32;
@@ -156,25 +206,26 @@ __device__ void setup_fit(const Params &p, FitGlobal *G, WGShared &S, bool use_p
             atomicOr(&S.mask[o >> 5], 1u << (o & 31));
         }
         __syncthreads();
-        if (t == 0) {
-            for (int w = kT - 1; w >= 0 && !S.sel_done; --w) {
-                uint32_t bits = S.mask[w];
-                while (bits && !S.sel_done) {
-                    const int b = 31 - __clz(bits);
-                    bits &= ~(1u << b);
-                    const int64_t j = lo + 32 * w + b;
-                    const double xj = p.cx[j], yj = p.cy[j], sj = p.cs[j];
-                    if (too_close(xj, yj, sj, x0, y0, s0, omega_b)) continue;
-                    bool close = false;
-                    for (int u = 0; u < S.nch && !close; ++u) {
-                        const int64_t mj = S.members[u + 1];
-                        close = too_close(xj, yj, sj, p.cx[mj], p.cy[mj], p.cs[mj], omega_b);
+        if (t < 64) {
+            // words from the highest index down: lane l holds word wbase + 63 - l
+            for (int wbase = kT - 64; wbase >= 0; wbase -= 64) {
+                const uint32_t word = S.mask[wbase + 63 - t];
+                unsigned long long nz = __ballot(word != 0u);
+                while (nz) {
+                    const int l = __ffsll((long long)nz) - 1;
+                    nz &= nz - 1ull;
+                    const uint32_t wv = __shfl(word, l, 64);
+                    if (t == 0 && !S.sel_done) {
+                        uint32_t bits = wv;
+                        while (bits && !S.sel_done) {
+                            const int b = 31 - __clz(bits);
+                            bits &= ~(1u << b);
+                            consider(p, S, lo + 32 * (wbase + 63 - l) + b, omega_b);
+                        }
                     }
-                    if (close) continue;
-                    S.members[1 + S.nch] = (int32_t)j;
-                    S.nch++;
-                    if (S.nch >= p.max_active - 1) S.sel_done = 1;
+                    if (__shfl(S.sel_done, 0, 64)) break;
                 }
+                if (__shfl(S.sel_done, 0, 64)) break;
             }
         }
     }
@@ -182,17 +233,19 @@ __device__ void setup_fit(const Params &p, FitGlobal *G, WGShared &S, bool use_p
     const int m = 1 + S.nch;
     if (t == 0) {
         S.members[0] = -1;
+        S.m = m;
+        S.n = 4 * m;
+        S.phase = 0;
+        S.trials = 0;
+        S.converged = 0;
         G->m = m;
         G->n = 4 * m;
-        G->phase = 0;
-        G->trials = 0;
-        G->converged = 0;
     }
     __syncthreads();
     if (t < m) {
         double th[4];
         if (t == 0) {
-            th[0] = a0; th[1] = x0; th[2] = y0; th[3] = s0;
+            th[0] = S.t0[0]; th[1] = S.t0[1]; th[2] = S.t0[2]; th[3] = S.t0[3];
         } else {
             const int64_t j = S.members[t];
             th[0] = p.ca[j]; th[1] = p.cx[j]; th[2] = p.cy[j]; th[3] = p.cs[j];
@@ -206,16 +259,17 @@ __device__ void setup_fit(const Params &p, FitGlobal *G, WGShared &S, bool use_p
         const double hi4[4] = {neg ? 0.0 : INFINITY, (double)w[3], (double)w[1], width_cap(p)};
         for (int q = 0; q < 4; ++q) {
             const int i = 4 * t + q;
-            G->lo[i] = lo4[q];
-            G->hi[i] = hi4[q];
-            G->th0[i] = th[q];
-            G->th_old[i] = (t == 0) ? 0.0 : th[q];
+            S.lo[i] = lo4[q];
+            S.hi[i] = hi4[q];
+            S.th0[i] = th[q];
+            S.th_old[i] = (t == 0) ? 0.0 : th[q];
             double v = th[q];
             if (!(v >= lo4[q])) v = lo4[q];
             if (v > hi4[q]) v = hi4[q];
+            S.th_e[i] = v;
             G->th_e[i] = v;
+            G->th_old[i] = S.th_old[i];
         }
-        G->members[t] = S.members[t];
     }
     __syncthreads();
 }
@@ -234,15 +288,18 @@ __device__ inline void out_pair(int o, int n, int &i, int &k)
     k = r + (o - start);
 }
 
-// Member constants at theta = G->th_e and the old members' stored Gaussians.
-__device__ void prepare(const Params &p, FitGlobal *G, WGShared &S)
+// Member constants at theta (th_e) and the old members' stored Gaussians
+// (th_old), from the published copy or from work-group 0's own.
+__device__ void prepare(const Params &p, WGShared &S, int m, const double *th_e,
+                        const double *th_old)
 {
     const int t = threadIdx.x;
-    if (t == 0) { S.m = G->m; S.n = G->n; }
+    __syncthreads();
+    if (t == 0) { S.m = m; S.n = 4 * m; }
     __syncthreads();
     if (t < S.m) {
-        const double a = G->th_e[4 * t], x = G->th_e[4 * t + 1], y = G->th_e[4 * t + 2],
-                     s = G->th_e[4 * t + 3];
+        const double a = th_e[4 * t], x = th_e[4 * t + 1], y = th_e[4 * t + 2],
+                     s = th_e[4 * t + 3];
         make_window(x, y, halfwidth(s, p.window_sigmas), p.H, p.W, S.win[t]);
         const double s2 = s * s;
         S.mx[t] = x;
@@ -252,8 +309,8 @@ __device__ void prepare(const Params &p, FitGlobal *G, WGShared &S)
         S.minvs2[t] = 1.0 / s2;
         S.minvs3[t] = 1.0 / (s2 * s);
         if (t > 0) {
-            const double oa = G->th_old[4 * t], ox = G->th_old[4 * t + 1],
-                         oy = G->th_old[4 * t + 2], os = G->th_old[4 * t + 3];
+            const double oa = th_old[4 * t], ox = th_old[4 * t + 1],
+                         oy = th_old[4 * t + 2], os = th_old[4 * t + 3];
             make_window(ox, oy, halfwidth(os, p.window_sigmas), p.H, p.W, S.wold[t]);
             S.ox[t] = ox;
             S.oy[t] = oy;
@@ -269,6 +326,12 @@ __device__ void prepare(const Params &p, FitGlobal *G, WGShared &S)
                                             (S.win[j][3] - S.win[j][2] + 1);
     }
     __syncthreads();
+}
+
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
 // Tiles tile0, tile0 + stride, ... of U; the work-group's partial (FP64:
@@ -299,27 +362,40 @@ __device__ void evaluate_tiles(const Params &p, WGShared &S, float *tile, double
 
     const int64_t total = S.pref[m];
     const int64_t ntiles = (total + kT - 1) / kT;
-    int64_t npx = 0;
-    double f_acc = 0.0, c_acc = 0.0;
+    double npx = 0.0, f_acc = 0.0, c_acc = 0.0;
     float *row = tile + t * kTileStride;
-    for (int64_t ti = tile0; ti < ntiles; ti += stride) {
+    // This thread's pixel of tile ti: coordinates, whether it is a first
+    // occurrence in U, and its residual value (loaded one tile ahead).
+    auto locate = [&](int64_t ti, int32_t &r, int32_t &c, bool &valid, float &rv) {
         const int64_t lin = ti * kT + t;
-        bool valid = false;
-        int32_t r = 0, c = 0;
-        if (lin < total) {
-            int w = 0;
-            while (lin >= S.pref[w + 1]) ++w;
-            const int64_t local = lin - S.pref[w];
-            const int32_t wc = S.win[w][3] - S.win[w][2] + 1;
-            r = S.win[w][0] + (int32_t)(local / wc);
-            c = S.win[w][2] + (int32_t)(local % wc);
-            valid = true;
-            for (int i = 0; i < w; ++i)
-                if (in_box(S.win[i], r, c)) { valid = false; break; }
-        }
+        valid = false;
+        r = 0;
+        c = 0;
+        rv = 0.0f;
+        if (ti >= ntiles || lin >= total) return;
+        int w = 0;
+        while (lin >= S.pref[w + 1]) ++w;
+        const int64_t local = lin - S.pref[w];
+        const int32_t wc = S.win[w][3] - S.win[w][2] + 1;
+        r = S.win[w][0] + (int32_t)(local / wc);
+        c = S.win[w][2] + (int32_t)(local % wc);
+        valid = true;
+        for (int i = 0; i < w; ++i)
+            if (in_box(S.win[i], r, c)) { valid = false; break; }
+        if (valid) rv = p.R[(int64_t)r * p.W + c];
+    };
+    int32_t nr_, nc_;
+    bool nvalid;
+    float nrv;
+    locate(tile0, nr_, nc_, nvalid, nrv);
+    for (int64_t ti = tile0; ti < ntiles; ti += stride) {
+        const int32_t r = nr_, c = nc_;
+        const bool valid = nvalid;
+        const float rv = nrv;
+        locate(ti + stride, nr_, nc_, nvalid, nrv);
         if (valid) {
-            ++npx;
-            double D = (double)p.R[(int64_t)r * p.W + c];
+            npx += 1.0;
+            double D = (double)rv;
             const double cd = (double)c, rd = (double)r;
             for (int j = 1; j < m; ++j) {
                 if (!in_box(S.wold[j], r, c)) continue;
@@ -348,20 +424,20 @@ __device__ void evaluate_tiles(const Params &p, WGShared &S, float *tile, double
             for (int k = 0; k <= n; ++k) row[k] = 0.0f;
         }
         __syncthreads();
+        // plain FP32 sum over the tile's pixels, Kahan-compensated across tiles
 #pragma unroll
         for (int u = 0; u < kOwnMax; ++u) {
             if (u >= n_own) break;
             const int ci = oi[u], ck = ok_[u];
-            float sum = acc_s[u], comp = acc_c[u];
+            float ts = 0.0f;
             for (int q = my_s; q < kT; q += S_sub) {
                 const float *rq = tile + q * kTileStride;
-                const float y = rq[ci] * rq[ck] - comp;
-                const float tt = sum + y;
-                comp = (tt - sum) - y;
-                sum = tt;
+                ts += rq[ci] * rq[ck];
             }
-            acc_s[u] = sum;
-            acc_c[u] = comp;
+            const float y = ts - acc_c[u];
+            const float tt = acc_s[u] + y;
+            acc_c[u] = (tt - acc_s[u]) - y;
+            acc_s[u] = tt;
         }
         __syncthreads();
     }
@@ -381,31 +457,138 @@ __device__ void evaluate_tiles(const Params &p, WGShared &S, float *tile, double
             out[t + u * kT] = (double)acc_s[u] - (double)acc_c[u];
         }
     }
-    // F, chi2 and the pixel count, summed over the threads in a fixed order
-    const double vals[3] = {f_acc, c_acc, (double)npx};
-    for (int q = 0; q < 3; ++q) {
-        __syncthreads();
-        red[t] = vals[q];
-        __syncthreads();
-        if (t == 0) {
-            double s = 0.0;
-            for (int i = 0; i < kT; ++i) s += red[i];
-            out[n_out + q] = s;
-        }
+    // F, chi2 and the pixel count: wave sums, then the four waves in order
+    const double f_w = wave_sum(f_acc), c_w = wave_sum(c_acc), p_w = wave_sum(npx);
+    if ((t & 63) == 0) {
+        S.wsum[t >> 6][0] = f_w;
+        S.wsum[t >> 6][1] = c_w;
+        S.wsum[t >> 6][2] = p_w;
+    }
+    __syncthreads();
+    if (t < 3) {
+        double v = 0.0;
+        for (int w = 0; w < kT / 64; ++w) v += S.wsum[w][t];
+        out[n_out + t] = v;
     }
     __syncthreads();
 }
 
-// Sum the partials of work-groups 0..geff-1 in that order into He, S.ge,
-// S.Fe, S.chi2e, S.npx_e.
-__device__ void reduce_partials(const Params &p, WGShared &S, int geff, double *He)
+// The same partial for fits of at most two members (n <= 8): each thread keeps
+// the 15 or 45 Gram entries of its own pixels in registers, Kahan-compensated,
+// with no barrier per tile; the threads' sums are combined once at the end by
+// wave shuffles and the four waves in order.
+template <int M>
+__device__ void evaluate_tiles_reg(const Params &p, WGShared &S, int64_t tile0, int64_t stride,
+                                   double *out)
 {
+    constexpr int N = 4 * M, C = N + 1, NO = C * (C + 1) / 2;
     const int t = threadIdx.x;
+    float acc_s[NO], acc_c[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) { acc_s[o] = 0.0f; acc_c[o] = 0.0f; }
+    double npx = 0.0, f_acc = 0.0, c_acc = 0.0;
+    const int64_t total = S.pref[M];
+    const int64_t ntiles = (total + kT - 1) / kT;
+    for (int64_t ti = tile0; ti < ntiles; ti += stride) {
+        const int64_t lin = ti * kT + t;
+        if (lin >= total) continue;
+        const int w = (M > 1 && lin >= S.pref[1]) ? 1 : 0;
+        const int32_t local = (int32_t)(lin - S.pref[w]);
+        const int32_t wc = S.win[w][3] - S.win[w][2] + 1;
+        const int32_t r = S.win[w][0] + local / wc;
+        const int32_t c = S.win[w][2] + local % wc;
+        if (M > 1 && w == 1 && in_box(S.win[0], r, c)) continue;
+        npx += 1.0;
+        double D = (double)p.R[(int64_t)r * p.W + c];
+        const double cd = (double)c, rd = (double)r;
+        if (M > 1 && in_box(S.wold[1], r, c)) {
+            const double dx = cd - S.ox[1], dy = rd - S.oy[1];
+            D += S.oamp[1] * exp(-(dx * dx + dy * dy) * S.oinv2[1]);
+        }
+        float col[C];
+        double Mv = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            if (!in_box(S.win[j], r, c)) {
+                col[4 * j] = col[4 * j + 1] = col[4 * j + 2] = col[4 * j + 3] = 0.0f;
+                continue;
+            }
+            const double dx = cd - S.mx[j], dy = rd - S.my[j];
+            const double q = dx * dx + dy * dy;
+            const double e = exp(-q * S.minv2[j]);
+            const double G = S.mamp[j] * e;
+            Mv += G;
+            col[4 * j] = (float)e;
+            col[4 * j + 1] = (float)(G * dx * S.minvs2[j]);
+            col[4 * j + 2] = (float)(G * dy * S.minvs2[j]);
+            col[4 * j + 3] = (float)(G * q * S.minvs3[j]);
+        }
+        const double res = D - Mv;
+        col[N] = (float)res;
+        f_acc += Mv * (Mv - 2.0 * D);
+        c_acc += res * res;
+        int o = 0;
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+#pragma unroll
+            for (int k = i; k < C; ++k, ++o) {
+                const float y = col[i] * col[k] - acc_c[o];
+                const float tt = acc_s[o] + y;
+                acc_c[o] = (tt - acc_s[o]) - y;
+                acc_s[o] = tt;
+            }
+    }
+    const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        const double v = wave_sum((double)acc_s[o] - (double)acc_c[o]);
+        if (lane == 0) S.wred[wave][o] = v;
+    }
+    const double f_w = wave_sum(f_acc), c_w = wave_sum(c_acc), p_w = wave_sum(npx);
+    if (lane == 0) {
+        S.wred[wave][NO] = f_w;
+        S.wred[wave][NO + 1] = c_w;
+        S.wred[wave][NO + 2] = p_w;
+    }
+    __syncthreads();
+    if (t < NO + 3) {
+        double v = 0.0;
+        for (int wv = 0; wv < kT / 64; ++wv) v += S.wred[wv][t];
+        out[t] = v;
+    }
+    __syncthreads();
+}
+
+// Rows w0..w1-1 of the partials summed in row order.
+__device__ inline double sum_column(const Params &p, int w0, int w1, int o)
+{
+    double v = 0.0;
+    int w = w0;
+    for (; w + 4 <= w1; w += 4) {
+        const double a = p.partials[(int64_t)w * kPartStride + o];
+        const double b = p.partials[(int64_t)(w + 1) * kPartStride + o];
+        const double c = p.partials[(int64_t)(w + 2) * kPartStride + o];
+        const double d = p.partials[(int64_t)(w + 3) * kPartStride + o];
+        v += a; v += b; v += c; v += d;
+    }
+    for (; w < w1; ++w) v += p.partials[(int64_t)w * kPartStride + o];
+    return v;
+}
+
+__device__ void sum_rows(const Params &p, int n, int w0, int w1, int dst)
+{
+    const int n_out = (n + 1) * (n + 2) / 2;
+    for (int o = threadIdx.x; o < n_out + 3; o += kT)
+        p.partials[(int64_t)dst * kPartStride + o] = sum_column(p, w0, w1, o);
+}
+
+// Rows w0..w1-1 summed in row order into He, S.ge, S.Fe, S.chi2e, S.npx_e.
+__device__ void reduce_partials(const Params &p, WGShared &S, int w0, int w1, double *He)
+{
     const int n = S.n;
     const int n_out = (n + 1) * (n + 2) / 2;
-    for (int o = t; o < n_out + 3; o += kT) {
-        double v = 0.0;
-        for (int w = 0; w < geff; ++w) v += p.partials[(int64_t)w * kPartStride + o];
+    for (int o = threadIdx.x; o < n_out + 3; o += kT) {
+        const double v = sum_column(p, w0, w1, o);
         if (o >= n_out) {
             if (o == n_out) S.Fe = v;
             else if (o == n_out + 1) S.chi2e = v;
@@ -463,40 +646,39 @@ __device__ bool chol_solve(WGShared &S, double *A, int n, double *b, double *x)
 }
 
 // ---------------------------------------------------------------------------
-// The LM bookkeeping (Marquardt 1963) after one evaluation, by the reducing
-// work-group.  Damped system (H + mu D) delta = g with
-// D = diag(max(H_ii, 1e-12 max H_ii)); a parameter on a bound whose gradient
-// leaves the box is held for the trial; the trial point is clipped to the
-// bounds; accept iff F decreases; gain-ratio damping (mu *= max(1/3,
-// 1 - (2 rho - 1)^3) on accept, mu *= nu, nu *= 2 on reject); converged when
-// an accepted step has max |delta_k| / scale_k < tol, or stalled once mu
-// passes 1e8; the budget counts trials.
-// Sets S.finished when the fit is over; otherwise G->th_e holds the next
-// trial.
+// The LM bookkeeping (Marquardt 1963) after one evaluation, work-group 0.
+// Damped system (H + mu D) delta = g with D = diag(max(H_ii, 1e-12 max
+// H_ii)); a parameter on a bound whose gradient leaves the box is held for
+// the trial; the trial point is clipped to the bounds; accept iff F
+// decreases; gain-ratio damping (mu *= max(1/3, 1 - (2 rho - 1)^3) on accept,
+// mu *= nu, nu *= 2 on reject); converged when an accepted step has
+// max |delta_k| / scale_k < tol, or stalled once mu passes 1e8; the budget
+// counts trials.  Sets S.finished when the fit is over; otherwise S.th_e
+// holds the next trial point.
 // ---------------------------------------------------------------------------
 
-__device__ void lm_step(const Params &p, FitGlobal *G, WGShared &S, double *He, double *A)
+__device__ void lm_step(const Params &p, WGShared &S, double *He, double *Hc, double *A)
 {
     const int t = threadIdx.x;
     const int n = S.n, m = S.m;
     if (t == 0) {
         S.finished = 0;
-        if (G->phase == 0) {
+        if (S.phase == 0) {
             S.accept = 1;
-            G->mu = p.lm_mu0;
-            G->nu = 2.0;
-            G->trials = 0;
-            G->converged = 0;
-            G->chi2_init = S.chi2e;
-            G->phase = 1;
+            S.mu = p.lm_mu0;
+            S.nu = 2.0;
+            S.trials = 0;
+            S.converged = 0;
+            S.chi2_init = S.chi2e;
+            S.phase = 1;
         } else {
             double Ft = S.Fe;
             if (!isfinite(Ft)) Ft = INFINITY;
-            S.accept = (Ft < G->F_c) ? 1 : 0;
+            S.accept = (Ft < S.F_c) ? 1 : 0;
             if (S.accept) {
                 double step = 0.0;
                 for (int j = 0; j < m; ++j) {
-                    const double *tn = G->th_e + 4 * j, *to = G->th_c + 4 * j;
+                    const double *tn = S.th_e + 4 * j, *to = S.th_c + 4 * j;
                     const double sa = fabs(tn[0]) > 1e-30 ? fabs(tn[0]) : 1e-30;
                     double v;
                     v = fabs(tn[0] - to[0]) / sa; step = v > step ? v : step;
@@ -504,106 +686,102 @@ __device__ void lm_step(const Params &p, FitGlobal *G, WGShared &S, double *He, 
                     v = fabs(tn[2] - to[2]) / tn[3]; step = v > step ? v : step;
                     v = fabs(tn[3] - to[3]) / tn[3]; step = v > step ? v : step;
                 }
-                const double rho = G->pred > 0.0 ? (G->F_c - Ft) / G->pred : 1.0;
+                const double rho = S.pred > 0.0 ? (S.F_c - Ft) / S.pred : 1.0;
                 const double tt = 2.0 * rho - 1.0;
                 double f = 1.0 - tt * tt * tt;
                 if (f < 1.0 / 3.0) f = 1.0 / 3.0;
-                G->mu *= f;
-                if (G->mu < 1e-12) G->mu = 1e-12;
-                G->nu = 2.0;
-                if (step < p.lm_tol) { G->converged = 1; S.finished = 1; }
+                S.mu *= f;
+                if (S.mu < 1e-12) S.mu = 1e-12;
+                S.nu = 2.0;
+                if (step < p.lm_tol) { S.converged = 1; S.finished = 1; }
             } else {
-                G->mu *= G->nu;
-                G->nu *= 2.0;
-                if (G->mu > 1e8) { G->converged = 1; S.finished = 1; }
+                S.mu *= S.nu;
+                S.nu *= 2.0;
+                if (S.mu > 1e8) { S.converged = 1; S.finished = 1; }
             }
         }
     }
     __syncthreads();
     if (S.accept) {
-        for (int e = t; e < n * n; e += kT) G->Hc[e] = He[e];
-        if (t < n) { G->th_c[t] = G->th_e[t]; G->g_c[t] = S.ge[t]; }
-        if (t == 0) { G->F_c = S.Fe; G->chi2_c = S.chi2e; G->npx_c = S.npx_e; }
-        // the reducer reads Hc back below: its own writes, ordered by the barrier
-        __threadfence_block();
+        for (int e = t; e < n * n; e += kT) Hc[e] = He[e];
+        if (t < n) { S.th_c[t] = S.th_e[t]; S.g_c[t] = S.ge[t]; }
+        if (t == 0) { S.F_c = S.Fe; S.chi2_c = S.chi2e; S.npx_c = S.npx_e; }
     }
     __syncthreads();
-    // next trial point, or finished
     for (;;) {
         __syncthreads();
         if (S.finished) break;
         if (t == 0) {
-            if (G->trials >= p.lm_max_iter) {
-                S.finished = 1;
-            } else {
-                double dmax = 0.0;
-                for (int i = 0; i < n; ++i) dmax = G->Hc[i * n + i] > dmax ? G->Hc[i * n + i] : dmax;
-                for (int i = 0; i < n; ++i) {
-                    const double d = G->Hc[i * n + i];
-                    S.dd[i] = d < 1e-12 * dmax ? 1e-12 * dmax : d;
-                    const double th = G->th_c[i], g = G->g_c[i];
-                    S.frozen[i] = ((th <= G->lo[i] && g <= 0.0) || (th >= G->hi[i] && g >= 0.0)) ? 1 : 0;
-                    S.rhs[i] = S.frozen[i] ? 0.0 : g;
-                }
-                G->trials++;
-            }
+            if (S.trials >= p.lm_max_iter) S.finished = 1;
+            else S.trials++;
+        }
+        if (t < n) {
+            double dmax = 0.0;
+            for (int i = 0; i < n; ++i) dmax = Hc[i * n + i] > dmax ? Hc[i * n + i] : dmax;
+            const double d = Hc[t * n + t];
+            S.dd[t] = d < 1e-12 * dmax ? 1e-12 * dmax : d;
+            const double th = S.th_c[t], g = S.g_c[t];
+            S.frozen[t] = ((th <= S.lo[t] && g <= 0.0) || (th >= S.hi[t] && g >= 0.0)) ? 1 : 0;
+            S.rhs[t] = S.frozen[t] ? 0.0 : g;
         }
         __syncthreads();
         if (S.finished) break;
-        const double mu = G->mu;
+        const double mu = S.mu;
         for (int e = t; e < n * n; e += kT) {
             const int i = e / n, k = e % n;
             double v;
             if (S.frozen[i] || S.frozen[k]) v = (i == k) ? 1.0 : 0.0;
-            else v = G->Hc[e] + (i == k ? mu * S.dd[i] : 0.0);
+            else v = Hc[e] + (i == k ? mu * S.dd[i] : 0.0);
             A[e] = v;
         }
         if (t < n) S.rhs_copy[t] = S.rhs[t];
         __syncthreads();
         const bool ok = chol_solve(S, A, n, S.rhs_copy, S.delta);
         if (ok) {
+            if (t < n) {
+                double v = S.th_c[t] + S.delta[t];
+                if (!(v >= S.lo[t])) v = S.lo[t];
+                if (v > S.hi[t]) v = S.hi[t];
+                S.th_e[t] = v;
+            }
             if (t == 0) {
                 double pred = 0.0;
-                for (int i = 0; i < n; ++i) {
-                    double v = G->th_c[i] + S.delta[i];
+                for (int i = 0; i < n; ++i)
                     pred += S.delta[i] * (S.rhs[i] + mu * S.dd[i] * S.delta[i]);
-                    if (!(v >= G->lo[i])) v = G->lo[i];
-                    if (v > G->hi[i]) v = G->hi[i];
-                    G->th_e[i] = v;
-                }
-                G->pred = pred;
+                S.pred = pred;
             }
             __syncthreads();
             break;
         }
         if (t == 0) {       // not positive definite: treated as a rejected trial
-            G->mu *= G->nu;
-            G->nu *= 2.0;
-            if (G->mu > 1e8) { G->converged = 1; S.finished = 1; }
+            S.mu *= S.nu;
+            S.nu *= 2.0;
+            if (S.mu > 1e8) { S.converged = 1; S.finished = 1; }
         }
     }
     __syncthreads();
 }
 
 // Commit (Sect. 3: the loop gain on the new component; refits replace the
-// old members) and the residual-update plan.  Whole work-group.
-__device__ void commit(const Params &p, FitGlobal *G, WGShared &S)
+// old members) and the residual-update plan.  Work-group 0.
+__device__ void commit(const Params &p, WGShared &S)
 {
     DevState *st = p.st;
     const int t = threadIdx.x;
     const int m = S.m;
     if (t == 0) {
         const int64_t L = st->L, k = st->k;
+        const int trials = S.trials_total + S.trials;
         st->n_active = m;
-        st->lm_iters = G->trials_total + G->trials;
-        st->converged = G->converged;
-        st->used_fallback = G->used_fallback;
-        st->chi2_init = G->chi2_init;
-        st->chi2_final = G->chi2_c;
-        st->fit_px = G->npx_c;
-        st->sum_trials += (unsigned long long)(G->trials_total + G->trials);
-        st->not_converged += G->converged ? 0ull : 1ull;
-        st->fallbacks += (unsigned long long)G->used_fallback;
+        st->lm_iters = trials;
+        st->converged = S.converged;
+        st->used_fallback = S.used_fallback;
+        st->chi2_init = S.chi2_init;
+        st->chi2_final = S.chi2_c;
+        st->fit_px = S.npx_c;
+        st->sum_trials += (unsigned long long)trials;
+        st->not_converged += S.converged ? 0ull : 1ull;
+        st->fallbacks += (unsigned long long)S.used_fallback;
         st->have_proposal = 0;
         int nr = 0;
         int32_t bb[4] = {INT32_MAX, -1, INT32_MAX, -1};
@@ -619,16 +797,16 @@ __device__ void commit(const Params &p, FitGlobal *G, WGShared &S)
             bb[3] = w[3] > bb[3] ? w[3] : bb[3];
         };
         for (int j = 1; j < m; ++j) {
-            const int64_t cj = G->members[j];
-            const double *to = G->th_old + 4 * j, *tn = G->th_c + 4 * j;
+            const int64_t cj = S.members[j];
+            const double *to = S.th_old + 4 * j, *tn = S.th_c + 4 * j;
             add_rect(to[0], to[1], to[2], to[3], +1.0f);
             add_rect(tn[0], tn[1], tn[2], tn[3], -1.0f);
             p.ca[cj] = tn[0]; p.cx[cj] = tn[1]; p.cy[cj] = tn[2]; p.cs[cj] = tn[3];
             p.c_updated[cj] = k;
         }
-        const double anew = p.gain * G->th_c[0];
-        add_rect(anew, G->th_c[1], G->th_c[2], G->th_c[3], -1.0f);
-        p.ca[L] = anew; p.cx[L] = G->th_c[1]; p.cy[L] = G->th_c[2]; p.cs[L] = G->th_c[3];
+        const double anew = p.gain * S.th_c[0];
+        add_rect(anew, S.th_c[1], S.th_c[2], S.th_c[3], -1.0f);
+        p.ca[L] = anew; p.cx[L] = S.th_c[1]; p.cy[L] = S.th_c[2]; p.cs[L] = S.th_c[3];
         p.c_added[L] = k;
         p.c_updated[L] = k;
         st->n_rects = nr;
@@ -638,130 +816,215 @@ __device__ void commit(const Params &p, FitGlobal *G, WGShared &S)
         st->k = k + 1;
         st->fit_ready = 1;
     }
-    if (t < m) st->members[t] = G->members[t];
+    if (t < m) st->members[t] = S.members[t];
     if (t < 4 * m) {
-        st->theta0[t] = G->th0[t];
-        st->theta[t] = G->th_c[t];
+        st->theta0[t] = S.th0[t];
+        st->theta[t] = S.th_c[t];
     }
     __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 
+// Evaluate this work-group's tiles of the trial prepared in S into row.
+__device__ void evaluate_row(const Params &p, WGShared &S, float *tile, double *red, int64_t tile0,
+                             int64_t stride, double *row)
+{
+    if (S.m == 1) evaluate_tiles_reg<1>(p, S, tile0, stride, row);
+    else if (S.m == 2) evaluate_tiles_reg<2>(p, S, tile0, stride, row);
+    else evaluate_tiles(p, S, tile, red, tile0, stride, row);
+}
+
+// Work-groups of a shared trial: at least kMinTiles tiles each.
+__device__ inline int eval_groups(int64_t ntiles, int nwg)
+{
+    const int64_t want = (ntiles + kMinTiles - 1) / kMinTiles;
+    return (int)(want < nwg ? want : nwg);
+}
+
+// Arrival of one work-group after a shared trial (every work-group, every
+// round): the last of a group sums the group's evaluated rows in order into
+// the group row and arrives at the top counter.
+__device__ void arrive(const Params &p, FitGlobal *G, WGShared &S, int wg, int nwg, int geff)
+{
+    const int t = threadIdx.x;
+    const int grp = wg / kGroup;
+    const int gsize = (grp + 1) * kGroup < nwg ? kGroup : nwg - grp * kGroup;
+    const int ng_eval = (geff + kGroup - 1) / kGroup;
+    release_fence();
+    __syncthreads();
+    if (t == 0) {
+        const unsigned prev = __hip_atomic_fetch_add(&G->arrive_g[grp], 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        S.last = (prev == (unsigned)gsize - 1u) ? 1 : 0;
+        if (S.last) {
+            __hip_atomic_store(&G->arrive_g[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+        }
+    }
+    __syncthreads();
+    if (!S.last) return;
+    const int r0 = grp * kGroup, r1 = (r0 + kGroup < geff) ? r0 + kGroup : geff;
+    if (ng_eval > 1 && r0 < r1) sum_rows(p, S.n, r0, r1, nwg + grp);
+    release_fence();
+    __syncthreads();
+    if (t == 0) __hip_atomic_fetch_add(&G->top, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ __launch_bounds__(kT) void k_fit(Params p)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     float *tile = reinterpret_cast<float *>(lds);
-    double *A = reinterpret_cast<double *>(tile + kT * kTileStride);
-    double *He = A + kMaxN * kMaxN;
-    double *red = He + kMaxN * kMaxN;
+    double *A = reinterpret_cast<double *>(lds);               // shares the tile buffer
+    double *He = reinterpret_cast<double *>(lds + kTileBytes);
+    double *Hc = He + kMaxN * kMaxN;
     __shared__ WGShared S;
+    __shared__ double red[kT];
     FitGlobal *G = p.fg;
     DevState *st = p.st;
     const int t = threadIdx.x;
     const int wg = blockIdx.x, nwg = gridDim.x;
+    const int ngroups = (nwg + kGroup - 1) / kGroup;
 
     // Nothing writes the stop flag before every work-group has checked in, so
     // all of them agree here.
     if (st->stop) return;
 
+    const unsigned long long t_start = now_ticks();
     // Check in: every work-group reads the generation before work-group 0 may
     // publish.
     if (t == 0) {
-        S.gen = __hip_atomic_load(&G->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        S.gen = __hip_atomic_load(&G->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         S.abort = 0;
-        __hip_atomic_fetch_add(&G->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&G->top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    if (wg == 0) {
-        if (t == 0) {
-            long it = 0;
-            while (__hip_atomic_load(&G->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                       (unsigned)nwg && it < kSpinLimit) {
-                __builtin_amdgcn_s_sleep(2);
-                ++it;
+
+    if (wg != 0) {
+        // Workers: evaluate the shared trials work-group 0 publishes.
+        for (;;) {
+            if (!wait_publish(G, S)) {
+                if (t == 0) st->stop = ASP_ERR_DEVICE;
+                return;
             }
-            S.abort = it >= kSpinLimit ? 1 : 0;
-            __threadfence();
-            __hip_atomic_store(&G->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // the peak and the stop test (Sect. 2 steps 1 and 4)
-            st->fit_ready = 0;
-            const unsigned long long key = st->peak_key;
-            st->peak_key = 0ull;
-            int64_t idx = st->forced_idx >= 0
-                              ? st->forced_idx
-                              : (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
-            const bool bad_idx = (st->forced_idx < 0 && key == 0ull) || idx < 0 || idx >= p.H * p.W;
-            st->forced_idx = -1;
-            S.stop = 0;
-            if (S.abort) S.stop = ASP_ERR_DEVICE;
-            else if (bad_idx) S.stop = ASP_ERR_STATE;
-            if (bad_idx) idx = 0;
-            const float v = p.R[idx];
-            if (S.stop == 0) {
-                if (fabs((double)v) < p.threshold) S.stop = ASP_STOP_THRESHOLD;
-                else if (st->k >= p.max_iter) S.stop = ASP_STOP_MAXITER;
-                else if (st->L >= p.cap) S.stop = ASP_ERR_CAPACITY;
-            }
-            st->idx = idx;
-            st->peak = v;
-            G->idx = idx;
-            G->peak = (double)v;
-            G->pass = 0;
-            G->trials_total = 0;
-            G->used_fallback = 0;
-            G->use_prop = (p.use_proposal && st->have_proposal) ? 1 : 0;
-            G->done = S.stop ? 1 : 0;
-            if (S.stop) st->stop = S.stop;
+            if (t == 0) S.done = G->done;
+            __syncthreads();
+            if (S.done) return;
+            prepare(p, S, G->m, G->th_e, G->th_old);
+            const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
+            const int geff = eval_groups(ntiles, nwg);
+            if (wg < geff)
+                evaluate_row(p, S, tile, red, wg, geff, p.partials + (int64_t)wg * kPartStride);
+            arrive(p, G, S, wg, nwg, geff);
         }
-        __syncthreads();
-        if (!S.stop) setup_fit(p, G, S, G->use_prop != 0);
-        publish(G);
     }
+
+    // Work-group 0 drives the fit.
+    if (t == 0) {
+        S.abort = spin_until(&G->top, (unsigned)nwg) ? 0 : 1;
+        __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicAdd(&st->prof[kPCheckin], now_ticks() - t_start);
+        atomicAdd(&st->prof[kPFits], 1ull);
+        // the peak and the stop test (Sect. 2 steps 1 and 4)
+        st->fit_ready = 0;
+        const unsigned long long key = st->peak_key;
+        st->peak_key = 0ull;
+        int64_t idx = st->forced_idx >= 0
+                          ? st->forced_idx
+                          : (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+        const bool bad_idx = (st->forced_idx < 0 && key == 0ull) || idx < 0 || idx >= p.H * p.W;
+        st->forced_idx = -1;
+        S.stop = 0;
+        if (S.abort) S.stop = ASP_ERR_DEVICE;
+        else if (bad_idx) S.stop = ASP_ERR_STATE;
+        if (bad_idx) idx = 0;
+        const float v = p.R[idx];
+        if (S.stop == 0) {
+            if (fabs((double)v) < p.threshold) S.stop = ASP_STOP_THRESHOLD;
+            else if (st->k >= p.max_iter) S.stop = ASP_STOP_MAXITER;
+            else if (st->L >= p.cap) S.stop = ASP_ERR_CAPACITY;
+        }
+        st->idx = idx;
+        st->peak = v;
+        S.idx = idx;
+        S.peak = (double)v;
+        S.pass = 0;
+        S.trials_total = 0;
+        S.used_fallback = 0;
+        S.use_prop = (p.use_proposal && st->have_proposal) ? 1 : 0;
+        // workers read this only after a publication of this fit
+        G->done = S.stop ? 1 : 0;
+        if (S.stop) st->stop = S.stop;
+    }
+    __syncthreads();
+    if (S.stop) {
+        publish(G);
+        return;
+    }
+    const unsigned long long t0s = now_ticks();
+    setup_fit(p, G, S, S.use_prop != 0);
+    if (t == 0) atomicAdd(&st->prof[kPSetup], now_ticks() - t0s);
     for (;;) {
-        if (!wait_publish(G, S)) {
-            if (t == 0) st->stop = ASP_ERR_DEVICE;
-            return;
-        }
-        if (t == 0) S.done = G->done;
-        __syncthreads();
-        if (S.done) return;
-        prepare(p, G, S);
+        // the trial at S.th_e
+        prepare(p, S, S.m, S.th_e, S.th_old);
         const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
-        const int geff = (int)(ntiles < nwg ? ntiles : nwg);
-        if (wg >= geff) continue;
-        evaluate_tiles(p, S, tile, red, wg, geff, p.partials + (int64_t)wg * kPartStride);
-        __threadfence();
-        __syncthreads();
-        if (t == 0) {
-            const unsigned prev =
-                __hip_atomic_fetch_add(&G->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            S.last = (prev == (unsigned)geff - 1u) ? 1 : 0;
-        }
-        __syncthreads();
-        if (!S.last) continue;
-        // The reducing work-group.
-        if (t == 0) __hip_atomic_store(&G->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        __syncthreads();
-        reduce_partials(p, S, geff, He);
-        lm_step(p, G, S, He, A);
-        if (S.finished) {
-            if (G->use_prop && !G->converged && G->pass == 0) {
-                // the learned start did not converge: the simple values instead
-                if (t == 0) {
-                    G->trials_total += G->trials;
-                    G->used_fallback = 1;
-                    G->pass = 1;
-                }
-                __syncthreads();
-                setup_fit(p, G, S, false);
-            } else {
-                commit(p, G, S);
-                if (t == 0) G->done = 1;
+        const unsigned long long te = now_ticks();
+        if (ntiles <= kSoloTiles) {
+            // small: work-group 0 alone, no publication
+            evaluate_row(p, S, tile, red, 0, 1, p.partials);
+            if (t == 0) atomicAdd(&st->prof[kPEval], now_ticks() - te);
+            reduce_partials(p, S, 0, 1, He);
+        } else {
+            // large: every work-group takes a share
+            const int geff = eval_groups(ntiles, nwg);
+            const int ng_eval = (geff + kGroup - 1) / kGroup;
+            if (t < S.n) G->th_e[t] = S.th_e[t];
+            publish(G);
+            evaluate_row(p, S, tile, red, 0, geff, p.partials);
+            if (t == 0) atomicAdd(&st->prof[kPEval], now_ticks() - te);
+            arrive(p, G, S, 0, nwg, geff);
+            const unsigned long long tw = now_ticks();
+            if (t == 0) {
+                S.abort = spin_until(&G->top, (unsigned)ngroups) ? 0 : 1;
+                __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                atomicAdd(&st->prof[kPWait], now_ticks() - tw);
             }
+            __syncthreads();
+            if (S.abort) {
+                if (t == 0) { st->stop = ASP_ERR_DEVICE; G->done = 1; }
+                publish(G);
+                return;
+            }
+            if (ng_eval > 1) reduce_partials(p, S, nwg, nwg + ng_eval, He);
+            else reduce_partials(p, S, 0, geff, He);
+        }
+        const unsigned long long tl = now_ticks();
+        lm_step(p, S, He, Hc, A);
+        if (t == 0) {
+            atomicAdd(&st->prof[kPLmStep], now_ticks() - tl);
+            atomicAdd(&st->prof[kPTrials], 1ull);
+            atomicAdd(&st->prof[kPEvalPx], (unsigned long long)S.npx_e);
+        }
+        if (!S.finished) continue;
+        if (S.use_prop && !S.converged && S.pass == 0) {
+            // the learned start did not converge: the simple values instead
+            if (t == 0) {
+                S.trials_total += S.trials;
+                S.used_fallback = 1;
+                S.pass = 1;
+            }
+            __syncthreads();
+            setup_fit(p, G, S, false);
+            continue;
+        }
+        const unsigned long long tc = now_ticks();
+        commit(p, S);
+        if (t == 0) {
+            G->done = 1;
+            atomicAdd(&st->prof[kPCommit], now_ticks() - tc);
         }
         publish(G);
+        return;
     }
 }
 
@@ -779,7 +1042,8 @@ int fit_grid_size(int device)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fit, kT, kFitLds) !=
             hipSuccess || per_cu < 1)
         return 1;
-    const int g = cus * per_cu;
+    int g = cus * per_cu;
+    if (g > kGroup * kMaxGroups) g = kGroup * kMaxGroups;
     return g < 1 ? 1 : g;
 }
 

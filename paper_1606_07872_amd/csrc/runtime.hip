@@ -151,7 +151,7 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     CREATE_HIP(dev_alloc(&c->work, np > 2 ? np : 2));
     const int fit_grid = asp::fit_grid_size(c->device);
     CREATE_HIP(dev_alloc(&c->fg, 1));
-    CREATE_HIP(dev_alloc(&c->partials, (size_t)fit_grid * asp::kPartStride));
+    CREATE_HIP(dev_alloc(&c->partials, (size_t)(fit_grid + asp::kMaxGroups) * asp::kPartStride));
     CREATE_HIP(hipMemsetAsync(c->fg, 0, sizeof(asp::FitGlobal), c->stream));
     CREATE_HIP(hipHostMalloc((void **)&c->st_host, sizeof(DevState), hipHostMallocDefault));
 
@@ -465,6 +465,21 @@ asp_status asp_psf_gauss(asp_ctx *c, double *alpha_b, double *omega_b)
     if (s != ASP_OK) return s;
     if (alpha_b) *alpha_b = c->st_host->alpha_b;
     if (omega_b) *omega_b = c->st_host->omega_b;
+    return ASP_OK;
+}
+
+asp_status asp_fit_profile(asp_ctx *c, double *out, int32_t n)
+{
+    if (!c || !out || n < 0 || n > asp::kProfSlots) return ASP_ERR_INVALID_ARG;
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    int rate_khz = 100000;
+    (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device);
+    const double us_per_tick = 1000.0 / (double)(rate_khz > 0 ? rate_khz : 100000);
+    for (int i = 0; i < n; ++i) {
+        const double v = (double)c->st_host->prof[i];
+        out[i] = (i < 7) ? v * us_per_tick : v;
+    }
     return ASP_OK;
 }
 
