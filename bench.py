@@ -2,16 +2,29 @@
 
 A step is one minor-cycle iteration: peak search, stop test, start values,
 active-set selection, LM fit, commit and residual update, all on the device.
-The workload is the 4096 x 4096 synthetic EVLA-like field (2000 points, 300
-Gaussians with sigma U[2, 120] px, Y-array PSF, active set <= 10, gain 0.1).
-Inputs are generated on the host, copied to HBM before the timed region, and
-the timed region runs K iterations after W warm-up iterations.
+The default workload is the 4096 x 4096 synthetic EVLA-like field (2000
+points, 300 Gaussians with sigma U[2, 120] px, Y-array PSF, active set <= 10,
+gain 0.1).  The images are generated on the host and copied to HBM before the
+timed region; the timed region runs K iterations after W warm-up iterations.
 
-Prints one JSON line.
+Besides the throughput the line carries:
+  roofline      the dominant kernel (the LM fit), timed with HIP events on the
+                context's stream over the timed region; its algorithmic work
+                is the FP32 Gram accumulation, (n+1)(n+2) flops per pixel
+                evaluation, against the FP32 vector peak
+  hbm           achieved HBM rates of the peak search (4 H W bytes per
+                launch) and of the residual update (8 bytes per pixel
+                read-modify-written)
+  cpu_baseline  the FP64 oracle, single-threaded, continuing the same run
+                from the state at the start of the timed region for a bounded
+                number of seconds
+
+Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +39,52 @@ WORKLOADS = {
     "c128": ("make_c128", 0),
 }
 
+PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X FP32 vector
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def fit_traffic(workload: str, fit_launches: int):
+    """HBM bytes per fit launch from the committed PMC summary, if it was taken
+    on the current fit kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"k_fit_{workload}_traffic.json")
+    src = os.path.join(ROOT, "paper_1606_07872_amd", "csrc", "fit.hip")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        with open(src, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("fit_hip_sha256") != digest:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(f, R0, comps0, k0, alpha_b, omega_b, seconds):
+    """The oracle continuing the run from (R0, comps0, k0) for about `seconds`."""
+    import oracle
+    o = oracle.Oracle(f.dirty, gain=f.gain, threshold=f.threshold, max_iter=f.max_iter,
+                      max_active=f.max_active, cap=f.max_iter + 1, alpha_b=alpha_b,
+                      omega_b=omega_b)
+    o.load_state(R0, comps0, k0)
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        r = o.step()
+        if r["status"] in (1, 2) or r["status"] < 0:    # a stop or an error; 3 = fit budget used
+            break
+        done += 1
+    secs = time.perf_counter() - t0
+    return {"value": done / secs if secs > 0 else 0.0, "unit": "iterations/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{done} iterations ({secs:.1f} s) of the same field continuing from "
+                      f"iteration {k0}, the state at the start of the timed region; FP64 C, "
+                      "one thread"}
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -34,13 +93,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="c4096", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-kernel-events", action="store_true",
+                    help="time without the per-launch event pairs")
+    ap.add_argument("--solo-tiles", type=int, default=0)
+    ap.add_argument("--min-tiles", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
-              "multi-GPU path", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the minor cycle "
+              "here has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1606_07872_amd as asp
@@ -49,17 +112,27 @@ def main():
     gen, seed = WORKLOADS[args.workload]
     t0 = time.time()
     f = getattr(skygen, gen)(seed)
-    print(f"[bench] generated {f.name} {f.shape} in {time.time() - t0:.1f}s", file=sys.stderr,
-          flush=True)
+    H, W = f.shape
+    log(f"generated {f.name} {f.shape} in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
     d_dirty = torch.from_numpy(f.dirty).cuda()
     d_psf = torch.from_numpy(f.psf).cuda()
     total = args.warmup + args.steps
     ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=max(f.max_iter, total),
-                      max_active=f.max_active)
+                      max_active=f.max_active, fit_solo_tiles=args.solo_tiles,
+                      fit_min_tiles=args.min_tiles)
     del d_dirty, d_psf
     torch.cuda.synchronize()
-    rc, wrep = ctx.run(args.warmup)
+    ctx.run(args.warmup)
+    torch.cuda.synchronize()
+    want_cpu = not args.no_cpu_baseline
+    if want_cpu:
+        R0 = ctx.residual()
+        comps0 = ctx.components_raw()
+        k0, _ = ctx.counts()
+        alpha_b, omega_b = ctx.psf_gauss()
+    prof0 = ctx.fit_profile()
+    ctx.kernel_timing(not args.no_kernel_events)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     rc, rep = ctx.run(args.steps)
@@ -68,9 +141,49 @@ def main():
     done = rep["iterations"]
     secs = t2 - t1
     value = done / secs if secs > 0 else 0.0
-    print(f"[bench] {done} iterations in {secs:.3f}s, trials {rep['lm_trials']}, "
-          f"not converged {rep['not_converged']}", file=sys.stderr, flush=True)
-    print(f"[bench] fit profile {ctx.fit_profile()}", file=sys.stderr, flush=True)
+    log(f"{done} iterations in {secs:.3f}s, trials {rep['lm_trials']}, "
+        f"not converged {rep['not_converged']}")
+    prof1 = ctx.fit_profile()
+    log("fit profile over the timed region " +
+        json.dumps({k: round(prof1[k] - prof0[k], 1) for k in prof1}))
+
+    roofline = None
+    hbm = None
+    if not args.no_kernel_events:
+        kt = ctx.kernel_times()
+        log(f"kernel times {kt}")
+        fit_ms, fit_n = kt["fit"]
+        peak_ms, peak_n = kt["peak"]
+        upd_ms, upd_n = kt["update"]
+        if fit_n and fit_ms > 0:
+            avg_s = fit_ms / fit_n * 1e-3
+            flops_per_launch = rep["gram_flops"] / fit_n
+            achieved = flops_per_launch / avg_s / 1e12
+            tr = fit_traffic(args.workload, fit_n)
+            roofline = {"kernel": "k_fit", "bound": "alu", "achieved": achieved,
+                        "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": tr,
+                        "avg_launch_us": avg_s * 1e6, "launches": fit_n,
+                        "work_per_launch": flops_per_launch,
+                        "share_of_step": fit_ms / (secs * 1e3)}
+        hbm = {}
+        if peak_n and peak_ms > 0:
+            b = 4.0 * H * W
+            gbs = b / (peak_ms / peak_n * 1e-3) / 1e9
+            hbm["k_peak"] = {"achieved_gbs": gbs, "frac": gbs / PEAK_HBM_GBS,
+                             "avg_launch_us": peak_ms / peak_n * 1e3, "bytes_per_launch": b}
+        if upd_n and upd_ms > 0:
+            b = 8.0 * rep["pixels_updated"] / upd_n
+            gbs = b / (upd_ms / upd_n * 1e-3) / 1e9
+            hbm["k_update"] = {"achieved_gbs": gbs, "frac": gbs / PEAK_HBM_GBS,
+                               "avg_launch_us": upd_ms / upd_n * 1e3, "bytes_per_launch": b}
+
+    cpu = None
+    if want_cpu:
+        log(f"oracle baseline for {args.cpu_seconds:.0f}s from iteration {k0}")
+        cpu = cpu_baseline(f, R0, comps0, k0, alpha_b, omega_b, args.cpu_seconds)
+        log(f"oracle {cpu['value']:.2f} iterations/s")
+
     line = {
         "metric": "minor-cycle iterations/s",
         "value": value,
@@ -82,12 +195,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pixels, f64 solve",
+        "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{f.name}: {f.shape[0]}x{f.shape[1]} FP32, active set <= "
-                               f"{f.max_active}, gain {f.gain}", "seed": f.seed},
-        "roofline": None,
-        "cpu_baseline": None,
+        "config": {"workload": f"{f.name}: {H}x{W} FP32 EVLA-like field, active set <= "
+                               f"{f.max_active}, gain {f.gain}, iterations "
+                               f"{args.warmup}..{args.warmup + done}", "seed": f.seed,
+                   "kernel_events": not args.no_kernel_events},
+        "roofline": roofline,
+        "hbm": hbm,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

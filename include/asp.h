@@ -101,6 +101,11 @@ typedef struct {
     int32_t lm_max_iter;         /* LM trial budget; default 100                 */
     int32_t init_mode;           /* 0 simple initial values, 1 learned proposal  */
     int32_t capacity;            /* component list size; 0 = max_iter            */
+    int32_t fit_solo_tiles;      /* LM trials over at most this many 256-pixel
+                                    tiles are evaluated by one work-group;
+                                    0 = default (8), -1 = never                  */
+    int32_t fit_min_tiles;       /* least tiles per work-group when a trial is
+                                    shared over the GPU; 0 = default (2)         */
     double window_sigmas;        /* window half-width factor c_w; default 5      */
     double max_width;            /* upper bound on s; 0 = max(omega_b, min(H,W)/8) */
     double lm_mu0;               /* initial damping; default 1e-3                */
@@ -116,6 +121,10 @@ typedef struct {
     int64_t lm_trials;           /* trials summed over this call's fits          */
     int64_t not_converged;       /* fits that used the whole budget              */
     int64_t fallbacks;           /* learned proposals replaced by simple values  */
+    int64_t pixels_updated;      /* pixels read-modify-written by the updates    */
+    int64_t pixels_evaluated;    /* pixel evaluations summed over the LM trials  */
+    int64_t gram_flops;          /* (n+1)(n+2) per pixel evaluation: the FP32
+                                    multiply-adds of [J r]^T [J r], n = 4 m      */
 } asp_run_report;
 
 /* Fill *opt with the defaults above. */
@@ -204,11 +213,20 @@ asp_status asp_psf_gauss(asp_ctx *ctx, double *alpha_b, double *omega_b);
 /* Iterations done (k) and components (L). */
 asp_status asp_counts(asp_ctx *ctx, int64_t *k, int64_t *L);
 
-/* Diagnostics: accumulated fit-kernel phase timers in microseconds and event
- * counts, n <= 10 entries: check-in, setup, evaluation (one work-group),
- * waits (one work-group), reduction, LM step, commit, trials, fits, pixels
- * evaluated.  Reading does not reset them. */
+/* Diagnostics: accumulated fit-kernel phase timers of the work-group that
+ * drives the fit, in microseconds, then event counts; n <= 12 entries:
+ * check-in, setup, evaluation, waits, reduction, LM step, commit, trial
+ * preparation, arrival, then trials, fits, pixels evaluated.  Reading does
+ * not reset them. */
 asp_status asp_fit_profile(asp_ctx *ctx, double *out, int32_t n);
+
+/* Diagnostics: per-kernel device time.  With timing on, asp_run and asp_step
+ * record a HIP event pair on the context's stream around every launch they
+ * make (which adds two event packets per launch); asp_kernel_times returns the
+ * summed milliseconds and launch counts, n <= 3 kinds: 0 peak search, 1 LM
+ * fit, 2 residual update.  Switching timing on or off clears the totals. */
+asp_status asp_kernel_timing(asp_ctx *ctx, int32_t on);
+asp_status asp_kernel_times(asp_ctx *ctx, double *ms, int64_t *launches, int32_t n);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,8 @@ MAX_ACTIVE = 16
 EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destroy",
            "asp_last_error", "asp_find_peak", "asp_fit_active_set", "asp_update_residual",
            "asp_step", "asp_run", "asp_components", "asp_components_raw", "asp_residual",
-           "asp_residual_device", "asp_psf_gauss", "asp_counts", "asp_fit_profile"]
+           "asp_residual_device", "asp_psf_gauss", "asp_counts", "asp_fit_profile",
+           "asp_kernel_timing", "asp_kernel_times"]
 
 
 class AspError(RuntimeError):
@@ -36,6 +37,7 @@ class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("max_active", ctypes.c_int32), ("lm_max_iter", ctypes.c_int32),
                 ("init_mode", ctypes.c_int32), ("capacity", ctypes.c_int32),
+                ("fit_solo_tiles", ctypes.c_int32), ("fit_min_tiles", ctypes.c_int32),
                 ("window_sigmas", ctypes.c_double), ("max_width", ctypes.c_double),
                 ("lm_mu0", ctypes.c_double), ("lm_tol", ctypes.c_double),
                 ("psf_lobe_frac", ctypes.c_double), ("stream", ctypes.c_void_p)]
@@ -68,7 +70,9 @@ class FitReport(ctypes.Structure):
 class RunReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("total_iterations", ctypes.c_int64),
                 ("components", ctypes.c_int64), ("lm_trials", ctypes.c_int64),
-                ("not_converged", ctypes.c_int64), ("fallbacks", ctypes.c_int64)]
+                ("not_converged", ctypes.c_int64), ("fallbacks", ctypes.c_int64),
+                ("pixels_updated", ctypes.c_int64), ("pixels_evaluated", ctypes.c_int64),
+                ("gram_flops", ctypes.c_int64)]
 
 
 COMPONENT_DTYPE = np.dtype([("flux", "<f8"), ("amp", "<f8"), ("x", "<f8"), ("y", "<f8"),
@@ -106,6 +110,8 @@ def lib():
         L.asp_residual_device.argtypes = [vp, P(vp)]
         L.asp_psf_gauss.argtypes = [vp, P(f64), P(f64)]
         L.asp_counts.argtypes = [vp, P(i64), P(i64)]
+        L.asp_kernel_timing.argtypes = [vp, ctypes.c_int32]
+        L.asp_kernel_times.argtypes = [vp, vp, vp, ctypes.c_int32]
         L.asp_fit_profile.argtypes = [vp, vp, ctypes.c_int32]
         for name in EXPORTS:
             if name not in ("asp_destroy", "asp_last_error"):
@@ -241,12 +247,25 @@ class Context:
         return p.value
 
     PROFILE_FIELDS = ("checkin_us", "setup_us", "eval_us", "wait_us", "reduce_us", "lmstep_us",
-                      "commit_us", "trials", "fits", "eval_px")
+                      "commit_us", "prepare_us", "arrive_us", "trials", "fits", "eval_px")
 
     def fit_profile(self) -> dict:
         out = np.zeros(len(self.PROFILE_FIELDS))
         self._check(lib().asp_fit_profile(self._ctx, out.ctypes.data, len(out)))
         return dict(zip(self.PROFILE_FIELDS, out.tolist()))
+
+    KERNEL_KINDS = ("peak", "fit", "update")
+
+    def kernel_timing(self, on: bool):
+        """Record HIP events around every launch of run()/step() (clears totals)."""
+        self._check(lib().asp_kernel_timing(self._ctx, 1 if on else 0))
+
+    def kernel_times(self) -> dict:
+        """{kind: (total ms, launches)} from the recorded event pairs."""
+        ms = np.zeros(3)
+        n = np.zeros(3, dtype=np.int64)
+        self._check(lib().asp_kernel_times(self._ctx, ms.ctypes.data, n.ctypes.data, 3))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNEL_KINDS)}
 
     def psf_gauss(self):
         a, w = ctypes.c_double(), ctypes.c_double()

@@ -24,7 +24,7 @@ struct Rect {
     int32_t pad;
 };
 
-constexpr int kProfSlots = 10;
+constexpr int kProfSlots = 12;
 
 // Mutable per-context state in device memory.
 struct DevState {
@@ -51,6 +51,9 @@ struct DevState {
     unsigned long long update_px;
     // counters summed over iterations
     unsigned long long sum_trials, not_converged, fallbacks;
+    unsigned long long sum_update_px;   // pixels read-modify-written by the update
+    unsigned long long sum_eval_px;     // pixel evaluations of the LM trials
+    unsigned long long sum_gram_flops;  // (n+1)(n+2) per pixel evaluation
     // Gaussian main lobe of the PSF
     double alpha_b, omega_b;
     int64_t lobe_px;
@@ -90,6 +93,8 @@ struct Params {
     double window_sigmas, max_width, lm_mu0, lm_tol;
     int32_t use_proposal;          // honour st->proposal when have_proposal
     int32_t fit_grid;              // work-groups of the fit kernel
+    int32_t solo_tiles;            // trials of at most this many tiles: work-group 0 alone
+    int32_t min_tiles;             // least tiles per work-group in a shared trial
     FitGlobal *fg;
     double *partials;              // fit_grid x kPartStride
 };

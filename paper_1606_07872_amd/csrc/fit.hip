@@ -35,14 +35,13 @@ constexpr size_t kTileBytes = sizeof(float) * kT * kTileStride;
 constexpr size_t kMatBytes = sizeof(double) * kMaxN * kMaxN;
 constexpr size_t kFitLds = kTileBytes + 2 * kMatBytes;   // tile (or A) | He | Hc
 constexpr long kSpinLimit = 1L << 22;
-constexpr int kMinTiles = 2;      // least tiles per evaluating work-group
-constexpr int kSoloTiles = 96;    // trials up to this many tiles: work-group 0 alone
 constexpr int kGroup = 16;        // work-groups per first-level arrival group
 static_assert(kTileBytes >= kMatBytes, "A shares the tile buffer");
 
 // Phase timer slots of DevState::prof.
-enum { kPCheckin = 0, kPSetup, kPEval, kPWait, kPReduce, kPLmStep, kPCommit, kPTrials, kPFits,
-       kPEvalPx };
+enum { kPCheckin = 0, kPSetup, kPEval, kPWait, kPReduce, kPLmStep, kPCommit, kPPrepare,
+       kPArrive, kPTrials, kPFits, kPEvalPx };
+static_assert(kPEvalPx + 1 == kProfSlots, "profile slots");
 
 __device__ inline unsigned long long now_ticks() { return wall_clock64(); }
 
@@ -71,17 +70,36 @@ struct WGShared {
     double t0[4];
     int32_t nch, sel_done;
     // control
+    unsigned long long tmark;      // phase timer mark (thread 0)
     unsigned int gen;
     int32_t last, abort, done, ok, finished, accept, stop;
 };
 
+// Phase timers of the driving work-group (thread 0): the mark lives in LDS so
+// that no tick value stays in registers across a phase.
+__device__ inline void mark(WGShared &S)
+{
+    if (threadIdx.x == 0) S.tmark = now_ticks();
+}
+
+__device__ __forceinline__ void lap(const Params &p, WGShared &S, int slot)
+{
+    if (threadIdx.x == 0) {
+        const unsigned long long now = now_ticks();
+        atomicAdd(&p.st->prof[slot], now - S.tmark);
+        S.tmark = now;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Synchronisation between work-groups.  Polling is relaxed (no cache
-// maintenance per poll); the fence after it is the acquire.  Before a
-// work-group signals, every thread issues a release fence for its own stores.
+// maintenance per poll); the fence after it is the acquire.  A work-group
+// signals after a barrier, by one release operation of thread 0.
 // ---------------------------------------------------------------------------
 
-__device__ bool wait_publish(FitGlobal *G, WGShared &S)
+__device__ inline void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+__device__ __forceinline__ bool wait_publish(FitGlobal *G, WGShared &S)
 {
     if (threadIdx.x == 0) {
         unsigned int now = S.gen;
@@ -92,24 +110,23 @@ __device__ bool wait_publish(FitGlobal *G, WGShared &S)
         }
         S.abort = (now == S.gen) ? 1 : 0;
         S.gen = now;
-        __threadfence();
+        acquire_fence();
     }
     __syncthreads();
     return S.abort == 0;
 }
 
-__device__ inline void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-
-__device__ void publish(FitGlobal *G)
+// The barrier makes every thread's stores visible to thread 0, whose release
+// at agent scope then covers them (the pattern of a grid-wide barrier).
+__device__ __forceinline__ void publish(FitGlobal *G)
 {
-    release_fence();
     __syncthreads();
     if (threadIdx.x == 0)
         __hip_atomic_fetch_add(&G->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Thread 0 waits until *ctr reaches target; returns false on timeout.
-__device__ bool spin_until(unsigned int *ctr, unsigned int target)
+__device__ __forceinline__ bool spin_until(unsigned int *ctr, unsigned int target)
 {
     long it = 0;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
@@ -117,7 +134,7 @@ __device__ bool spin_until(unsigned int *ctr, unsigned int target)
         __builtin_amdgcn_s_sleep(1);
         ++it;
     }
-    __threadfence();
+    acquire_fence();
     return it < kSpinLimit;
 }
 
@@ -140,7 +157,7 @@ __device__ inline bool too_close(double xj, double yj, double sj, double xm, dou
 }
 
 // Lane 0 of wave 0: greedy acceptance of candidate j.
-__device__ inline void consider(const Params &p, WGShared &S, int64_t j, double omega_b)
+__device__ __forceinline__ void consider(const Params &p, WGShared &S, int64_t j, double omega_b)
 {
     const double xj = p.cx[j], yj = p.cy[j], sj = p.cs[j];
     if (too_close(xj, yj, sj, S.t0[1], S.t0[2], S.t0[3], omega_b)) return;
@@ -155,7 +172,7 @@ __device__ inline void consider(const Params &p, WGShared &S, int64_t j, double 
 
 // Start values, active set, bounds; the start point goes to S.th_e and is
 // published in G.  Work-group 0, whole work-group.
-__device__ void setup_fit(const Params &p, FitGlobal *G, WGShared &S, bool use_prop)
+__device__ __forceinline__ void setup_fit(const Params &p, FitGlobal *G, WGShared &S, bool use_prop)
 {
     const int t = threadIdx.x;
     const double omega_b = p.st->omega_b;
@@ -290,7 +307,7 @@ __device__ inline void out_pair(int o, int n, int &i, int &k)
 
 // Member constants at theta (th_e) and the old members' stored Gaussians
 // (th_old), from the published copy or from work-group 0's own.
-__device__ void prepare(const Params &p, WGShared &S, int m, const double *th_e,
+__device__ __forceinline__ void prepare(const Params &p, WGShared &S, int m, const double *th_e,
                         const double *th_old)
 {
     const int t = threadIdx.x;
@@ -336,7 +353,7 @@ __device__ inline double wave_sum(double v)
 
 // Tiles tile0, tile0 + stride, ... of U; the work-group's partial (FP64:
 // n_out Gram entries, F, chi2, the pixel count) goes to out.
-__device__ void evaluate_tiles(const Params &p, WGShared &S, float *tile, double *red,
+__device__ __forceinline__ void evaluate_tiles(const Params &p, WGShared &S, float *tile, double *red,
                                int64_t tile0, int64_t stride, double *out)
 {
     const int t = threadIdx.x;
@@ -478,7 +495,7 @@ __device__ void evaluate_tiles(const Params &p, WGShared &S, float *tile, double
 // with no barrier per tile; the threads' sums are combined once at the end by
 // wave shuffles and the four waves in order.
 template <int M>
-__device__ void evaluate_tiles_reg(const Params &p, WGShared &S, int64_t tile0, int64_t stride,
+__device__ __forceinline__ void evaluate_tiles_reg(const Params &p, WGShared &S, int64_t tile0, int64_t stride,
                                    double *out)
 {
     constexpr int N = 4 * M, C = N + 1, NO = C * (C + 1) / 2;
@@ -560,7 +577,7 @@ __device__ void evaluate_tiles_reg(const Params &p, WGShared &S, int64_t tile0, 
 }
 
 // Rows w0..w1-1 of the partials summed in row order.
-__device__ inline double sum_column(const Params &p, int w0, int w1, int o)
+__device__ __forceinline__ double sum_column(const Params &p, int w0, int w1, int o)
 {
     double v = 0.0;
     int w = w0;
@@ -575,7 +592,7 @@ __device__ inline double sum_column(const Params &p, int w0, int w1, int o)
     return v;
 }
 
-__device__ void sum_rows(const Params &p, int n, int w0, int w1, int dst)
+__device__ __forceinline__ void sum_rows(const Params &p, int n, int w0, int w1, int dst)
 {
     const int n_out = (n + 1) * (n + 2) / 2;
     for (int o = threadIdx.x; o < n_out + 3; o += kT)
@@ -583,7 +600,7 @@ __device__ void sum_rows(const Params &p, int n, int w0, int w1, int dst)
 }
 
 // Rows w0..w1-1 summed in row order into He, S.ge, S.Fe, S.chi2e, S.npx_e.
-__device__ void reduce_partials(const Params &p, WGShared &S, int w0, int w1, double *He)
+__device__ __forceinline__ void reduce_partials(const Params &p, WGShared &S, int w0, int w1, double *He)
 {
     const int n = S.n;
     const int n_out = (n + 1) * (n + 2) / 2;
@@ -657,49 +674,153 @@ __device__ bool chol_solve(WGShared &S, double *A, int n, double *b, double *x)
 // holds the next trial point.
 // ---------------------------------------------------------------------------
 
-__device__ void lm_step(const Params &p, WGShared &S, double *He, double *Hc, double *A)
+// Acceptance of the evaluated trial and the damping update (thread 0).
+__device__ __forceinline__ void lm_accept(const Params &p, WGShared &S)
+{
+    const int m = S.m;
+    S.finished = 0;
+    if (S.phase == 0) {
+        S.accept = 1;
+        S.mu = p.lm_mu0;
+        S.nu = 2.0;
+        S.trials = 0;
+        S.converged = 0;
+        S.chi2_init = S.chi2e;
+        S.phase = 1;
+        return;
+    }
+    double Ft = S.Fe;
+    if (!isfinite(Ft)) Ft = INFINITY;
+    S.accept = (Ft < S.F_c) ? 1 : 0;
+    if (S.accept) {
+        double step = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double *tn = S.th_e + 4 * j, *to = S.th_c + 4 * j;
+            const double sa = fabs(tn[0]) > 1e-30 ? fabs(tn[0]) : 1e-30;
+            double v;
+            v = fabs(tn[0] - to[0]) / sa; step = v > step ? v : step;
+            v = fabs(tn[1] - to[1]) / tn[3]; step = v > step ? v : step;
+            v = fabs(tn[2] - to[2]) / tn[3]; step = v > step ? v : step;
+            v = fabs(tn[3] - to[3]) / tn[3]; step = v > step ? v : step;
+        }
+        const double rho = S.pred > 0.0 ? (S.F_c - Ft) / S.pred : 1.0;
+        const double tt = 2.0 * rho - 1.0;
+        double f = 1.0 - tt * tt * tt;
+        if (f < 1.0 / 3.0) f = 1.0 / 3.0;
+        S.mu *= f;
+        if (S.mu < 1e-12) S.mu = 1e-12;
+        S.nu = 2.0;
+        if (step < p.lm_tol) { S.converged = 1; S.finished = 1; }
+    } else {
+        S.mu *= S.nu;
+        S.nu *= 2.0;
+        if (S.mu > 1e8) { S.converged = 1; S.finished = 1; }
+    }
+}
+
+// The damped solve for n = N <= 8 by thread 0 alone, the factor's lower
+// triangle in registers: the same arithmetic as the work-group path below,
+// with each Cholesky column scaled by one reciprocal square root.
+template <int N>
+__device__ __forceinline__ void lm_solve_small(int32_t lm_max_iter, WGShared &S, const double *He,
+                                               double *Hc)
+{
+    if (S.accept) {
+        for (int e = 0; e < N * N; ++e) Hc[e] = He[e];
+#pragma unroll
+        for (int i = 0; i < N; ++i) { S.th_c[i] = S.th_e[i]; S.g_c[i] = S.ge[i]; }
+        S.F_c = S.Fe; S.chi2_c = S.chi2e; S.npx_c = S.npx_e;
+    }
+    double dmax = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) dmax = Hc[i * N + i] > dmax ? Hc[i * N + i] : dmax;
+    double dd[N], rhs[N];
+    bool fr[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double hii = Hc[i * N + i];
+        dd[i] = hii < 1e-12 * dmax ? 1e-12 * dmax : hii;
+        const double th = S.th_c[i], g = S.g_c[i];
+        fr[i] = (th <= S.lo[i] && g <= 0.0) || (th >= S.hi[i] && g >= 0.0);
+        rhs[i] = fr[i] ? 0.0 : g;
+    }
+    while (!S.finished) {
+        if (S.trials >= lm_max_iter) { S.finished = 1; break; }
+        S.trials++;
+        const double mu = S.mu;
+        double a[N][N];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int k = 0; k <= i; ++k)
+                a[i][k] = (fr[i] || fr[k]) ? (i == k ? 1.0 : 0.0)
+                                           : Hc[i * N + k] + (i == k ? mu * dd[i] : 0.0);
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double d = a[k][k];
+            ok = ok && d > 0.0 && isfinite(d);
+            const double r = ok ? 1.0 / sqrt(d) : 0.0;
+            a[k][k] = ok ? d * r : 1.0;
+#pragma unroll
+            for (int i = k + 1; i < N; ++i) a[i][k] *= r;
+#pragma unroll
+            for (int i = k + 1; i < N; ++i)
+#pragma unroll
+                for (int j = k + 1; j <= i; ++j) a[i][j] -= a[i][k] * a[j][k];
+        }
+        double x[N];
+        if (ok) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                double v = rhs[i];
+#pragma unroll
+                for (int j = 0; j < i; ++j) v -= a[i][j] * x[j];
+                x[i] = v / a[i][i];
+            }
+#pragma unroll
+            for (int i = N - 1; i >= 0; --i) {
+                double v = x[i];
+#pragma unroll
+                for (int j = i + 1; j < N; ++j) v -= a[j][i] * x[j];
+                x[i] = v / a[i][i];
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) ok = ok && isfinite(x[i]);
+        }
+        if (ok) {
+            double pred = 0.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                double v = S.th_c[i] + x[i];
+                if (!(v >= S.lo[i])) v = S.lo[i];
+                if (v > S.hi[i]) v = S.hi[i];
+                S.th_e[i] = v;
+                S.delta[i] = x[i];
+                pred += x[i] * (rhs[i] + mu * dd[i] * x[i]);
+            }
+            S.pred = pred;
+            break;
+        }
+        // not positive definite: treated as a rejected trial
+        S.mu *= S.nu;
+        S.nu *= 2.0;
+        if (S.mu > 1e8) { S.converged = 1; S.finished = 1; }
+    }
+}
+
+__device__ __forceinline__ void lm_step(const Params &p, WGShared &S, double *He, double *Hc, double *A)
 {
     const int t = threadIdx.x;
-    const int n = S.n, m = S.m;
-    if (t == 0) {
-        S.finished = 0;
-        if (S.phase == 0) {
-            S.accept = 1;
-            S.mu = p.lm_mu0;
-            S.nu = 2.0;
-            S.trials = 0;
-            S.converged = 0;
-            S.chi2_init = S.chi2e;
-            S.phase = 1;
-        } else {
-            double Ft = S.Fe;
-            if (!isfinite(Ft)) Ft = INFINITY;
-            S.accept = (Ft < S.F_c) ? 1 : 0;
-            if (S.accept) {
-                double step = 0.0;
-                for (int j = 0; j < m; ++j) {
-                    const double *tn = S.th_e + 4 * j, *to = S.th_c + 4 * j;
-                    const double sa = fabs(tn[0]) > 1e-30 ? fabs(tn[0]) : 1e-30;
-                    double v;
-                    v = fabs(tn[0] - to[0]) / sa; step = v > step ? v : step;
-                    v = fabs(tn[1] - to[1]) / tn[3]; step = v > step ? v : step;
-                    v = fabs(tn[2] - to[2]) / tn[3]; step = v > step ? v : step;
-                    v = fabs(tn[3] - to[3]) / tn[3]; step = v > step ? v : step;
-                }
-                const double rho = S.pred > 0.0 ? (S.F_c - Ft) / S.pred : 1.0;
-                const double tt = 2.0 * rho - 1.0;
-                double f = 1.0 - tt * tt * tt;
-                if (f < 1.0 / 3.0) f = 1.0 / 3.0;
-                S.mu *= f;
-                if (S.mu < 1e-12) S.mu = 1e-12;
-                S.nu = 2.0;
-                if (step < p.lm_tol) { S.converged = 1; S.finished = 1; }
-            } else {
-                S.mu *= S.nu;
-                S.nu *= 2.0;
-                if (S.mu > 1e8) { S.converged = 1; S.finished = 1; }
-            }
+    const int n = S.n;
+    if (t == 0) lm_accept(p, S);
+    if (n <= 8) {
+        if (t == 0) {
+            if (n == 4) lm_solve_small<4>(p.lm_max_iter, S, He, Hc);
+            else lm_solve_small<8>(p.lm_max_iter, S, He, Hc);
         }
+        __syncthreads();
+        return;
     }
     __syncthreads();
     if (S.accept) {
@@ -764,7 +885,7 @@ __device__ void lm_step(const Params &p, WGShared &S, double *He, double *Hc, do
 
 // Commit (Sect. 3: the loop gain on the new component; refits replace the
 // old members) and the residual-update plan.  Work-group 0.
-__device__ void commit(const Params &p, WGShared &S)
+__device__ __forceinline__ void commit(const Params &p, WGShared &S)
 {
     DevState *st = p.st;
     const int t = threadIdx.x;
@@ -827,7 +948,7 @@ __device__ void commit(const Params &p, WGShared &S)
 // ---------------------------------------------------------------------------
 
 // Evaluate this work-group's tiles of the trial prepared in S into row.
-__device__ void evaluate_row(const Params &p, WGShared &S, float *tile, double *red, int64_t tile0,
+__device__ __forceinline__ void evaluate_row(const Params &p, WGShared &S, float *tile, double *red, int64_t tile0,
                              int64_t stride, double *row)
 {
     if (S.m == 1) evaluate_tiles_reg<1>(p, S, tile0, stride, row);
@@ -835,38 +956,34 @@ __device__ void evaluate_row(const Params &p, WGShared &S, float *tile, double *
     else evaluate_tiles(p, S, tile, red, tile0, stride, row);
 }
 
-// Work-groups of a shared trial: at least kMinTiles tiles each.
-__device__ inline int eval_groups(int64_t ntiles, int nwg)
+// Work-groups of a shared trial: at least min_tiles tiles each.
+__device__ inline int eval_groups(int64_t ntiles, int nwg, int min_tiles)
 {
-    const int64_t want = (ntiles + kMinTiles - 1) / kMinTiles;
+    const int64_t want = (ntiles + min_tiles - 1) / min_tiles;
     return (int)(want < nwg ? want : nwg);
 }
 
 // Arrival of one work-group after a shared trial (every work-group, every
 // round): the last of a group sums the group's evaluated rows in order into
 // the group row and arrives at the top counter.
-__device__ void arrive(const Params &p, FitGlobal *G, WGShared &S, int wg, int nwg, int geff)
+__device__ __forceinline__ void arrive(const Params &p, FitGlobal *G, WGShared &S, int wg, int nwg, int geff)
 {
     const int t = threadIdx.x;
     const int grp = wg / kGroup;
     const int gsize = (grp + 1) * kGroup < nwg ? kGroup : nwg - grp * kGroup;
     const int ng_eval = (geff + kGroup - 1) / kGroup;
-    release_fence();
     __syncthreads();
     if (t == 0) {
         const unsigned prev = __hip_atomic_fetch_add(&G->arrive_g[grp], 1u, __ATOMIC_ACQ_REL,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         S.last = (prev == (unsigned)gsize - 1u) ? 1 : 0;
-        if (S.last) {
+        if (S.last)
             __hip_atomic_store(&G->arrive_g[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-        }
     }
     __syncthreads();
     if (!S.last) return;
     const int r0 = grp * kGroup, r1 = (r0 + kGroup < geff) ? r0 + kGroup : geff;
     if (ng_eval > 1 && r0 < r1) sum_rows(p, S.n, r0, r1, nwg + grp);
-    release_fence();
     __syncthreads();
     if (t == 0) __hip_atomic_fetch_add(&G->top, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -890,7 +1007,7 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
     // all of them agree here.
     if (st->stop) return;
 
-    const unsigned long long t_start = now_ticks();
+    mark(S);
     // Check in: every work-group reads the generation before work-group 0 may
     // publish.
     if (t == 0) {
@@ -912,7 +1029,7 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
             if (S.done) return;
             prepare(p, S, G->m, G->th_e, G->th_old);
             const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
-            const int geff = eval_groups(ntiles, nwg);
+            const int geff = eval_groups(ntiles, nwg, p.min_tiles);
             if (wg < geff)
                 evaluate_row(p, S, tile, red, wg, geff, p.partials + (int64_t)wg * kPartStride);
             arrive(p, G, S, wg, nwg, geff);
@@ -923,7 +1040,7 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
     if (t == 0) {
         S.abort = spin_until(&G->top, (unsigned)nwg) ? 0 : 1;
         __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        atomicAdd(&st->prof[kPCheckin], now_ticks() - t_start);
+        lap(p, S, kPCheckin);
         atomicAdd(&st->prof[kPFits], 1ull);
         // the peak and the stop test (Sect. 2 steps 1 and 4)
         st->fit_ready = 0;
@@ -961,34 +1078,35 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
         publish(G);
         return;
     }
-    const unsigned long long t0s = now_ticks();
+    mark(S);
     setup_fit(p, G, S, S.use_prop != 0);
-    if (t == 0) atomicAdd(&st->prof[kPSetup], now_ticks() - t0s);
+    lap(p, S, kPSetup);
     for (;;) {
         // the trial at S.th_e
         prepare(p, S, S.m, S.th_e, S.th_old);
         const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
-        const unsigned long long te = now_ticks();
-        if (ntiles <= kSoloTiles) {
+        lap(p, S, kPPrepare);
+        if (ntiles <= p.solo_tiles) {
             // small: work-group 0 alone, no publication
             evaluate_row(p, S, tile, red, 0, 1, p.partials);
-            if (t == 0) atomicAdd(&st->prof[kPEval], now_ticks() - te);
+            lap(p, S, kPEval);
             reduce_partials(p, S, 0, 1, He);
+            lap(p, S, kPReduce);
         } else {
             // large: every work-group takes a share
-            const int geff = eval_groups(ntiles, nwg);
+            const int geff = eval_groups(ntiles, nwg, p.min_tiles);
             const int ng_eval = (geff + kGroup - 1) / kGroup;
             if (t < S.n) G->th_e[t] = S.th_e[t];
             publish(G);
             evaluate_row(p, S, tile, red, 0, geff, p.partials);
-            if (t == 0) atomicAdd(&st->prof[kPEval], now_ticks() - te);
+            lap(p, S, kPEval);
             arrive(p, G, S, 0, nwg, geff);
-            const unsigned long long tw = now_ticks();
+            lap(p, S, kPArrive);
             if (t == 0) {
                 S.abort = spin_until(&G->top, (unsigned)ngroups) ? 0 : 1;
                 __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                atomicAdd(&st->prof[kPWait], now_ticks() - tw);
             }
+            lap(p, S, kPWait);
             __syncthreads();
             if (S.abort) {
                 if (t == 0) { st->stop = ASP_ERR_DEVICE; G->done = 1; }
@@ -997,13 +1115,16 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
             }
             if (ng_eval > 1) reduce_partials(p, S, nwg, nwg + ng_eval, He);
             else reduce_partials(p, S, 0, geff, He);
+            lap(p, S, kPReduce);
         }
-        const unsigned long long tl = now_ticks();
         lm_step(p, S, He, Hc, A);
+        lap(p, S, kPLmStep);
         if (t == 0) {
-            atomicAdd(&st->prof[kPLmStep], now_ticks() - tl);
+            const unsigned long long npx = (unsigned long long)S.npx_e;
+            st->sum_eval_px += npx;
+            st->sum_gram_flops += npx * (unsigned long long)((S.n + 1) * (S.n + 2));
             atomicAdd(&st->prof[kPTrials], 1ull);
-            atomicAdd(&st->prof[kPEvalPx], (unsigned long long)S.npx_e);
+            atomicAdd(&st->prof[kPEvalPx], npx);
         }
         if (!S.finished) continue;
         if (S.use_prop && !S.converged && S.pass == 0) {
@@ -1017,12 +1138,10 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
             setup_fit(p, G, S, false);
             continue;
         }
-        const unsigned long long tc = now_ticks();
+        mark(S);
         commit(p, S);
-        if (t == 0) {
-            G->done = 1;
-            atomicAdd(&st->prof[kPCommit], now_ticks() - tc);
-        }
+        lap(p, S, kPCommit);
+        if (t == 0) G->done = 1;
         publish(G);
         return;
     }

@@ -175,7 +175,10 @@ __global__ __launch_bounds__(256) void k_update(Params p)
     __syncthreads();
     if (t == 0) {
         unsigned long long c = cnt_s[0] + cnt_s[1] + cnt_s[2] + cnt_s[3];
-        if (c) atomicAdd(&st->update_px, c);
+        if (c) {
+            atomicAdd(&st->update_px, c);
+            atomicAdd(&st->sum_update_px, c);
+        }
     }
 }
 

@@ -9,6 +9,7 @@
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "asp_device.h"
 
@@ -34,6 +35,12 @@ struct asp_ctx {
     Params P{};
     int peak_grid = 1024, update_grid = 1024;
     int phase = 0;                        // 0 ready, 1 peak found, 2 fitted
+    // kernel timing: event pairs around the launches of asp_run
+    bool timing = false;
+    std::vector<hipEvent_t> events;       // 2 per launch slot
+    std::vector<int> ev_kind;             // kind of each recorded pair
+    double t_ms[3] = {0.0, 0.0, 0.0};
+    int64_t t_n[3] = {0, 0, 0};
     std::string err;
 };
 
@@ -69,6 +76,7 @@ void release(asp_ctx *c)
     (void)hipFree(c->st); (void)hipFree(c->work); (void)hipFree(c->comp_out);
     (void)hipFree(c->fg); (void)hipFree(c->partials);
     if (c->st_host) (void)hipHostFree(c->st_host);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
 }
 
@@ -103,6 +111,7 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     }
     if (opt.max_iter < 0 || opt.max_active < 1 || opt.max_active > ASP_MAX_ACTIVE ||
         opt.lm_max_iter < 1 || opt.init_mode < 0 || opt.init_mode > 1 || opt.capacity < 0 ||
+        opt.fit_solo_tiles < -1 || opt.fit_min_tiles < 0 ||
         !(opt.window_sigmas > 0.0) || !(opt.max_width >= 0.0) || !(opt.lm_mu0 > 0.0) ||
         !(opt.lm_tol > 0.0) || !(opt.psf_lobe_frac > 0.0 && opt.psf_lobe_frac < 1.0))
         return ASP_ERR_INVALID_ARG;
@@ -208,6 +217,8 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     P.lm_tol = opt.lm_tol;
     P.use_proposal = 1;
     P.fit_grid = fit_grid;
+    P.solo_tiles = opt.fit_solo_tiles == 0 ? 8 : opt.fit_solo_tiles;
+    P.min_tiles = opt.fit_min_tiles == 0 ? 2 : opt.fit_min_tiles;
     P.fg = c->fg;
     P.partials = c->partials;
     *out = c;
@@ -221,6 +232,49 @@ asp_status stop_status(const asp_ctx *c)
     if (s == ASP_STOP_THRESHOLD || s == ASP_STOP_MAXITER) return (asp_status)s;
     if (s < 0) return (asp_status)s;
     return ASP_OK;
+}
+
+// Timed launch: an event pair around the launch when timing is on.
+template <typename F>
+asp_status timed(asp_ctx *c, int kind, F launch)
+{
+    if (!c->timing) {
+        HIP_OR_FAIL(c, launch());
+        return ASP_OK;
+    }
+    const size_t slot = c->ev_kind.size();
+    while (c->events.size() < 2 * (slot + 1)) {
+        hipEvent_t e;
+        HIP_OR_FAIL(c, hipEventCreate(&e));
+        c->events.push_back(e);
+    }
+    HIP_OR_FAIL(c, hipEventRecord(c->events[2 * slot], c->stream));
+    HIP_OR_FAIL(c, launch());
+    HIP_OR_FAIL(c, hipEventRecord(c->events[2 * slot + 1], c->stream));
+    c->ev_kind.push_back(kind);
+    return ASP_OK;
+}
+
+// Fold the recorded pairs into the per-kind totals (the stream has drained).
+asp_status harvest(asp_ctx *c)
+{
+    for (size_t i = 0; i < c->ev_kind.size(); ++i) {
+        float ms = 0.0f;
+        HIP_OR_FAIL(c, hipEventElapsedTime(&ms, c->events[2 * i], c->events[2 * i + 1]));
+        c->t_ms[c->ev_kind[i]] += (double)ms;
+        c->t_n[c->ev_kind[i]] += 1;
+    }
+    c->ev_kind.clear();
+    return ASP_OK;
+}
+
+asp_status enqueue_iteration(asp_ctx *c)
+{
+    asp_status s = timed(c, 0, [&] { return asp::launch_peak(c->P, c->peak_grid, c->stream); });
+    if (s == ASP_OK) s = timed(c, 1, [&] { return asp::launch_fit(c->P, c->stream); });
+    if (s == ASP_OK)
+        s = timed(c, 2, [&] { return asp::launch_update(c->P, c->update_grid, c->stream); });
+    return s;
 }
 
 }  // namespace
@@ -343,14 +397,6 @@ asp_status asp_update_residual(asp_ctx *c, int64_t *pixels_touched)
     return ASP_OK;
 }
 
-static asp_status enqueue_iteration(asp_ctx *c)
-{
-    HIP_OR_FAIL(c, asp::launch_peak(c->P, c->peak_grid, c->stream));
-    HIP_OR_FAIL(c, asp::launch_fit(c->P, c->stream));
-    HIP_OR_FAIL(c, asp::launch_update(c->P, c->update_grid, c->stream));
-    return ASP_OK;
-}
-
 asp_status asp_step(asp_ctx *c)
 {
     if (!c) return ASP_ERR_INVALID_ARG;
@@ -358,6 +404,8 @@ asp_status asp_step(asp_ctx *c)
     asp_status s = enqueue_iteration(c);
     if (s != ASP_OK) return s;
     s = pull_all(c);
+    if (s != ASP_OK) return s;
+    s = harvest(c);
     if (s != ASP_OK) return s;
     return stop_status(c);
 }
@@ -370,7 +418,8 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
     if (s != ASP_OK) return s;
     const int64_t k0 = c->st_host->k;
     const unsigned long long t0 = c->st_host->sum_trials, nc0 = c->st_host->not_converged,
-                             fb0 = c->st_host->fallbacks;
+                             fb0 = c->st_host->fallbacks, up0 = c->st_host->sum_update_px,
+                             ep0 = c->st_host->sum_eval_px, gf0 = c->st_host->sum_gram_flops;
     int64_t done = 0;
     asp_status result = stop_status(c);
     while (result == ASP_OK && done < n_iter) {
@@ -380,6 +429,8 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
             if (s != ASP_OK) return s;
         }
         s = pull_all(c);
+        if (s != ASP_OK) return s;
+        s = harvest(c);
         if (s != ASP_OK) return s;
         const int64_t before = done;
         done = c->st_host->k - k0;
@@ -394,6 +445,9 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
         rep->lm_trials = (int64_t)(c->st_host->sum_trials - t0);
         rep->not_converged = (int64_t)(c->st_host->not_converged - nc0);
         rep->fallbacks = (int64_t)(c->st_host->fallbacks - fb0);
+        rep->pixels_updated = (int64_t)(c->st_host->sum_update_px - up0);
+        rep->pixels_evaluated = (int64_t)(c->st_host->sum_eval_px - ep0);
+        rep->gram_flops = (int64_t)(c->st_host->sum_gram_flops - gf0);
     }
     return result;
 }
@@ -478,8 +532,28 @@ asp_status asp_fit_profile(asp_ctx *c, double *out, int32_t n)
     const double us_per_tick = 1000.0 / (double)(rate_khz > 0 ? rate_khz : 100000);
     for (int i = 0; i < n; ++i) {
         const double v = (double)c->st_host->prof[i];
-        out[i] = (i < 7) ? v * us_per_tick : v;
+        out[i] = (i < 9) ? v * us_per_tick : v;   // 9 timers, then counts
     }
+    return ASP_OK;
+}
+
+asp_status asp_kernel_timing(asp_ctx *c, int32_t on)
+{
+    if (!c || on < 0 || on > 1) return ASP_ERR_INVALID_ARG;
+    if (!c->ev_kind.empty()) {
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        asp_status s = harvest(c);
+        if (s != ASP_OK) return s;
+    }
+    c->timing = on != 0;
+    for (int i = 0; i < 3; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
+    return ASP_OK;
+}
+
+asp_status asp_kernel_times(asp_ctx *c, double *ms, int64_t *launches, int32_t n)
+{
+    if (!c || n < 0 || n > 3 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
+    for (int i = 0; i < n; ++i) { ms[i] = c->t_ms[i]; launches[i] = c->t_n[i]; }
     return ASP_OK;
 }
 

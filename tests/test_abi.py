@@ -27,6 +27,14 @@ def test_library_exports_every_symbol():
         assert hasattr(L, name), name
 
 
+def test_binding_declares_every_signature():
+    """Every export has its argument types declared: ctypes would otherwise pass
+    pointers as 32-bit ints."""
+    L = asp.lib()
+    for name in asp.EXPORTS:
+        assert getattr(L, name).argtypes is not None, name
+
+
 def test_default_options():
     opt = asp.default_options()
     assert opt.struct_size == ctypes.sizeof(asp.Options)
