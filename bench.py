@@ -98,6 +98,8 @@ def main():
                     help="time without the per-launch event pairs")
     ap.add_argument("--solo-tiles", type=int, default=0)
     ap.add_argument("--min-tiles", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the minor cycle "
@@ -105,6 +107,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        n = 64 << 20                        # floats: 256 MiB read and 256 MiB written
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "copies": 3}), flush=True)
+        return
 
     import paper_1606_07872_amd as asp
     import skygen
