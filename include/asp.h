@@ -92,6 +92,10 @@ typedef struct {
     double theta0[4 * ASP_MAX_ACTIVE];   /* start (a, x, y, s) per member        */
     double theta[4 * ASP_MAX_ACTIVE];    /* fitted, before the loop gain         */
     int64_t fit_px;              /* pixels in the union of windows at the fit    */
+    int32_t init_source;         /* start of the new component: 0 simple values,
+                                    1 the caller's init, 2 the network           */
+    int32_t pad2;
+    double init[4];              /* the proposal (a, x, y, s) before clamping     */
 } asp_fit_report;
 
 typedef struct {
@@ -204,6 +208,9 @@ asp_status asp_components_raw(asp_ctx *ctx, double *out4, int64_t cap, int64_t *
 
 /* Copy the residual to a host buffer of H*W floats. */
 asp_status asp_residual(asp_ctx *ctx, float *out);
+/* Sum over the image of residual^2, in FP64 and a fixed order, on the
+ * device (no copy of the image). */
+asp_status asp_residual_sumsq(asp_ctx *ctx, double *sum_sq);
 /* Device pointer of the residual (valid until asp_destroy). */
 asp_status asp_residual_device(asp_ctx *ctx, float **dev);
 
@@ -220,11 +227,76 @@ asp_status asp_counts(asp_ctx *ctx, int64_t *k, int64_t *L);
  * not reset them. */
 asp_status asp_fit_profile(asp_ctx *ctx, double *out, int32_t n);
 
+/*
+ * Learned start values.  A perceptron 1024 -> 256 -> 256 -> 4 (ReLU) maps the
+ * 32 x 32 residual patch around the peak (rows r*-16..r*+15, columns
+ * c*-16..c*+15, zero outside the image, divided by R[p*]) to
+ * (a / R[p*], log(s / omega_b), x - c*, y - r*) of the new component, which
+ * replaces the simple initial values of Sect. 3 as the start of the LM fit;
+ * when that fit does not converge the simple values are fitted instead.
+ * Weights are FP32 in the order W1 (256 x 1024, row-major), b1, W2
+ * (256 x 256), b2, W3 (4 x 256), b3: ASP_MLP_PARAMS values.
+ */
+#define ASP_MLP_PARAMS 329220
+#define ASP_MLP_IN 1024
+#define ASP_MLP_OUT 4
+
+/* Give the context a network (host array of n = ASP_MLP_PARAMS floats,
+ * copied). */
+asp_status asp_set_mlp(asp_ctx *ctx, const float *weights, int64_t n);
+/* 0: simple initial values; 1: the network (needs asp_set_mlp). */
+asp_status asp_set_init_mode(asp_ctx *ctx, int32_t mode);
+
+/*
+ * Record a training pair per iteration into caller-owned device buffers:
+ * patches (cap x 1024 FP32, the network's input), targets (cap x 4 FP32, the
+ * fitted new component before the loop gain, encoded as the network's
+ * output) and flags (cap int32: bit 0 converged, bit 1 fallback used, bits
+ * 2-3 init_source).  Recording covers asp_run, asp_step and the step API; it
+ * stops when cap pairs are stored.  cap = 0 turns it off.  The buffers must
+ * stay valid while recording is on.
+ */
+asp_status asp_record(asp_ctx *ctx, float *patches_dev, float *targets_dev, int32_t *flags_dev,
+                      int64_t cap);
+asp_status asp_record_count(asp_ctx *ctx, int64_t *n);
+
+/*
+ * Training on the device (forward and backward passes and Adam by the
+ * library's own kernels, FP32).  The loss of a batch is the mean over samples
+ * and outputs of (y - t)^2.
+ *   asp_mlp_create    weights from a host array of ASP_MLP_PARAMS floats
+ *                     (copied); batches of at most max_batch rows; stream NULL
+ *                     = own stream.  Adam moments start at zero.
+ *   asp_mlp_loss_grad loss and gradient of one batch (device x: batch x 1024,
+ *                     t: batch x 4); grad (host, ASP_MLP_PARAMS, nullable)
+ *                     is in the weights' order.  No update.
+ *   asp_mlp_train     n_steps Adam steps (lr, beta1 0.9, beta2 0.999, eps
+ *                     1e-8) on batches of `batch` rows of (x, t) (device,
+ *                     n_rows rows each) picked by order (device int32,
+ *                     n_steps x batch row indices; an index outside
+ *                     [0, n_rows) is an ASP_ERR_INVALID_ARG); *mean_loss is
+ *                     the mean batch loss.
+ *   asp_mlp_forward   outputs (device, rows x 4) for device inputs rows x 1024.
+ *   asp_mlp_weights   the current weights to a host array.
+ */
+typedef struct asp_mlp asp_mlp;
+asp_status asp_mlp_create(const float *init, int32_t max_batch, void *stream, asp_mlp **out);
+void asp_mlp_destroy(asp_mlp *net);
+const char *asp_mlp_last_error(const asp_mlp *net);
+asp_status asp_mlp_loss_grad(asp_mlp *net, const float *x_dev, const float *t_dev, int32_t batch,
+                             double *loss, float *grad);
+asp_status asp_mlp_train(asp_mlp *net, const float *x_dev, const float *t_dev, int64_t n_rows,
+                         const int32_t *order_dev, int64_t n_steps, int32_t batch, float lr,
+                         double *mean_loss);
+asp_status asp_mlp_forward(asp_mlp *net, const float *x_dev, int64_t rows, float *y_dev);
+asp_status asp_mlp_weights(asp_mlp *net, float *out);
+
 /* Diagnostics: per-kernel device time.  With timing on, asp_run and asp_step
  * record a HIP event pair on the context's stream around every launch they
  * make (which adds two event packets per launch); asp_kernel_times returns the
- * summed milliseconds and launch counts, n <= 3 kinds: 0 peak search, 1 LM
- * fit, 2 residual update.  Switching timing on or off clears the totals. */
+ * summed milliseconds and launch counts, n <= 4 kinds: 0 peak search, 1 LM
+ * fit, 2 residual update, 3 proposal / patch recording.  Switching timing on
+ * or off clears the totals. */
 asp_status asp_kernel_timing(asp_ctx *ctx, int32_t on);
 asp_status asp_kernel_times(asp_ctx *ctx, double *ms, int64_t *launches, int32_t n);
 

@@ -480,8 +480,10 @@ int orc_psf_fit(const double *psf, int64_t Hp, int64_t Wp, double main_lobe_frac
 /* ------------------------------------------------------------------------ */
 /* Active set (the paper names an active-set heuristic but defines it in     */
 /* the 2004 paper, which is not available).  Reading: candidates are         */
-/* existing components whose amplitude has the sign of the new component's  */
-/* (zero excluded) and whose centre lies inside the new component's window,  */
+/* existing components whose amplitude has the sign of the peak (zero       */
+/* excluded) and whose centre lies inside the window of the simple start    */
+/* (peak pixel, omega_b) whatever the new component's start value, so the   */
+/* set depends on the peak and the component list only; they are            */
 /* taken most recent first up to K_max - 1 (with the sign bounds of the fit, */
 /* no two members can cancel each other); a                                  */
 /* candidate is skipped when it is too close to a member already taken (the */
@@ -555,15 +557,18 @@ static void set_bounds(fit_problem *fp, const double *theta)
     }
 }
 
-static int fit_from(const orc_state *st, const double *init4, orc_report *rep, double *theta,
-                    lm_result *out, double *hess_out)
+/* The active set depends on the peak and the component list only: it is
+ * selected around the simple start `sel` (peak value, peak pixel, omega_b)
+ * whatever the start `init4` of the new component. */
+static int fit_from(const orc_state *st, const double *init4, const double *sel,
+                    orc_report *rep, double *theta, lm_result *out, double *hess_out)
 {
     double t0[4];
     memcpy(t0, init4, sizeof t0);
-    int64_t wnew[4];
-    comp_window(st, t0[1], t0[2], t0[3], wnew);
+    int64_t wsel[4];
+    comp_window(st, sel[1], sel[2], sel[3], wsel);
     int32_t chosen[ORC_MAX_ACTIVE];
-    int nch = select_active(st, t0, wnew, chosen);
+    int nch = select_active(st, sel, wsel, chosen);
     fit_problem fp;
     memset(&fp, 0, sizeof fp);
     fp.st = st;
@@ -620,7 +625,7 @@ int orc_step(orc_state *st, const double *init, orc_report *rep, double *hess_ou
     if (init) {
         /* A proposal: width at least omega_b, centre within 16 px of the peak. */
         double p4[4] = {init[0], init[1], init[2], init[3]};
-        if (!isfinite(p4[0])) p4[0] = pv;
+        if (!(p4[0] * pv > 0.0)) p4[0] = pv;     /* the peak's sign; also NaN */
         if (!(p4[1] >= (double)pc - 16.0)) p4[1] = (double)pc - 16.0;
         if (p4[1] > (double)pc + 16.0) p4[1] = (double)pc + 16.0;
         if (!(p4[2] >= (double)pr - 16.0)) p4[2] = (double)pr - 16.0;
@@ -631,18 +636,18 @@ int orc_step(orc_state *st, const double *init, orc_report *rep, double *hess_ou
         if (p4[2] > (double)(st->H - 1)) p4[2] = (double)(st->H - 1);
         if (!(p4[3] >= st->omega_b)) p4[3] = st->omega_b;
         if (p4[3] > width_max(st)) p4[3] = width_max(st);
-        rc = fit_from(st, p4, rep, theta, &lmr, hess_out);
+        rc = fit_from(st, p4, plain, rep, theta, &lmr, hess_out);
         if (rc != ORC_OK) return rep->status = rc;
         if (!lmr.converged) {
             /* The simple initial values are the fallback. */
             used_fallback = 1;
             int tr = lmr.trials;
-            rc = fit_from(st, plain, rep, theta, &lmr, hess_out);
+            rc = fit_from(st, plain, plain, rep, theta, &lmr, hess_out);
             if (rc != ORC_OK) return rep->status = rc;
             lmr.trials += tr;
         }
     } else {
-        rc = fit_from(st, plain, rep, theta, &lmr, hess_out);
+        rc = fit_from(st, plain, plain, rep, theta, &lmr, hess_out);
         if (rc != ORC_OK) return rep->status = rc;
     }
     int m = rep->n_active;

@@ -24,7 +24,14 @@ EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destro
            "asp_last_error", "asp_find_peak", "asp_fit_active_set", "asp_update_residual",
            "asp_step", "asp_run", "asp_components", "asp_components_raw", "asp_residual",
            "asp_residual_device", "asp_psf_gauss", "asp_counts", "asp_fit_profile",
-           "asp_kernel_timing", "asp_kernel_times"]
+           "asp_kernel_timing", "asp_kernel_times", "asp_set_mlp", "asp_set_init_mode",
+           "asp_record", "asp_record_count", "asp_mlp_create", "asp_mlp_destroy",
+           "asp_mlp_last_error", "asp_mlp_loss_grad", "asp_mlp_train", "asp_mlp_forward",
+           "asp_mlp_weights", "asp_residual_sumsq"]
+
+MLP_PARAMS = 329220
+MLP_IN = 1024
+MLP_OUT = 4
 
 
 class AspError(RuntimeError):
@@ -64,7 +71,8 @@ class FitReport(ctypes.Structure):
                 ("chi2_init", ctypes.c_double), ("chi2_final", ctypes.c_double),
                 ("theta0", ctypes.c_double * (4 * MAX_ACTIVE)),
                 ("theta", ctypes.c_double * (4 * MAX_ACTIVE)),
-                ("fit_px", ctypes.c_int64)]
+                ("fit_px", ctypes.c_int64), ("init_source", ctypes.c_int32),
+                ("pad2", ctypes.c_int32), ("init", ctypes.c_double * 4)]
 
 
 class RunReport(ctypes.Structure):
@@ -112,9 +120,24 @@ def lib():
         L.asp_counts.argtypes = [vp, P(i64), P(i64)]
         L.asp_kernel_timing.argtypes = [vp, ctypes.c_int32]
         L.asp_kernel_times.argtypes = [vp, vp, vp, ctypes.c_int32]
+        L.asp_set_mlp.argtypes = [vp, vp, i64]
+        L.asp_set_init_mode.argtypes = [vp, ctypes.c_int32]
+        L.asp_record.argtypes = [vp, vp, vp, vp, i64]
+        L.asp_record_count.argtypes = [vp, P(i64)]
+        L.asp_mlp_create.argtypes = [vp, ctypes.c_int32, vp, P(vp)]
+        L.asp_mlp_destroy.argtypes = [vp]
+        L.asp_mlp_destroy.restype = None
+        L.asp_mlp_last_error.argtypes = [vp]
+        L.asp_mlp_last_error.restype = ctypes.c_char_p
+        L.asp_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int32, P(f64), vp]
+        L.asp_mlp_train.argtypes = [vp, vp, vp, i64, vp, i64, ctypes.c_int32, f32, P(f64)]
+        L.asp_mlp_forward.argtypes = [vp, vp, i64, vp]
+        L.asp_mlp_weights.argtypes = [vp, vp]
+        L.asp_residual_sumsq.argtypes = [vp, P(f64)]
         L.asp_fit_profile.argtypes = [vp, vp, ctypes.c_int32]
         for name in EXPORTS:
-            if name not in ("asp_destroy", "asp_last_error"):
+            if name not in ("asp_destroy", "asp_last_error", "asp_mlp_destroy",
+                            "asp_mlp_last_error"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -241,6 +264,12 @@ class Context:
         self._check(lib().asp_residual(self._ctx, out.ctypes.data))
         return out
 
+    def residual_rms(self) -> float:
+        """sqrt(mean residual^2), reduced on the device in FP64."""
+        v = ctypes.c_double()
+        self._check(lib().asp_residual_sumsq(self._ctx, ctypes.byref(v)))
+        return float(np.sqrt(v.value / (self.H * self.W)))
+
     def residual_device_ptr(self) -> int:
         p = ctypes.c_void_p()
         self._check(lib().asp_residual_device(self._ctx, ctypes.byref(p)))
@@ -254,7 +283,7 @@ class Context:
         self._check(lib().asp_fit_profile(self._ctx, out.ctypes.data, len(out)))
         return dict(zip(self.PROFILE_FIELDS, out.tolist()))
 
-    KERNEL_KINDS = ("peak", "fit", "update")
+    KERNEL_KINDS = ("peak", "fit", "update", "propose")
 
     def kernel_timing(self, on: bool):
         """Record HIP events around every launch of run()/step() (clears totals)."""
@@ -262,15 +291,116 @@ class Context:
 
     def kernel_times(self) -> dict:
         """{kind: (total ms, launches)} from the recorded event pairs."""
-        ms = np.zeros(3)
-        n = np.zeros(3, dtype=np.int64)
-        self._check(lib().asp_kernel_times(self._ctx, ms.ctypes.data, n.ctypes.data, 3))
+        ms = np.zeros(4)
+        n = np.zeros(4, dtype=np.int64)
+        self._check(lib().asp_kernel_times(self._ctx, ms.ctypes.data, n.ctypes.data, 4))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNEL_KINDS)}
+
+    # -- learned start values ------------------------------------------------
+    def set_mlp(self, weights):
+        """Give the context the proposal network (flat FP32 weights, see Mlp)."""
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        self._check(lib().asp_set_mlp(self._ctx, w.ctypes.data, w.size))
+
+    def set_init_mode(self, mode: int):
+        """0 simple initial values, 1 the network's proposal."""
+        self._check(lib().asp_set_init_mode(self._ctx, int(mode)))
+
+    def record(self, patches, targets, flags):
+        """Record a (patch, target, flag) triple per iteration into device tensors
+        of shapes (cap, 1024) f32, (cap, 4) f32 and (cap,) int32; None turns it off."""
+        if patches is None:
+            self._check(lib().asp_record(self._ctx, None, None, None, 0))
+            self._rec = None
+            return
+        cap = int(patches.shape[0])
+        if tuple(patches.shape) != (cap, MLP_IN) or tuple(targets.shape) != (cap, MLP_OUT) \
+                or tuple(flags.shape) != (cap,):
+            raise ValueError("record buffers must be (cap, 1024), (cap, 4) and (cap,)")
+        for t, dt in ((patches, "float32"), (targets, "float32"), (flags, "int32")):
+            if not (_is_device_tensor(t) and str(t.dtype).endswith(dt) and t.is_contiguous()):
+                raise ValueError("record buffers must be contiguous device tensors")
+        self._rec = (patches, targets, flags)        # keep them alive
+        self._check(lib().asp_record(self._ctx, patches.data_ptr(), targets.data_ptr(),
+                                     flags.data_ptr(), cap))
+
+    def record_count(self) -> int:
+        n = ctypes.c_int64()
+        self._check(lib().asp_record_count(self._ctx, ctypes.byref(n)))
+        return n.value
 
     def psf_gauss(self):
         a, w = ctypes.c_double(), ctypes.c_double()
         self._check(lib().asp_psf_gauss(self._ctx, ctypes.byref(a), ctypes.byref(w)))
         return a.value, w.value
+
+
+class Mlp:
+    """The proposal network's trainer on the device (forward and backward passes
+    and Adam by the library's kernels).  Inputs are contiguous FP32 device
+    tensors; weights come in and go out as flat host arrays."""
+
+    def __init__(self, weights, max_batch: int = 512, stream=None):
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        if w.size != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} weights")
+        self._n = ctypes.c_void_p()
+        rc = lib().asp_mlp_create(w.ctypes.data, int(max_batch),
+                                  None if stream is None else ctypes.c_void_p(stream),
+                                  ctypes.byref(self._n))
+        if rc != ASP_OK:
+            raise AspError(rc, "asp_mlp_create failed")
+        self.max_batch = int(max_batch)
+
+    def close(self):
+        if self._n:
+            lib().asp_mlp_destroy(self._n)
+            self._n = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc < 0:
+            raise AspError(rc, lib().asp_mlp_last_error(self._n).decode())
+        return rc
+
+    @staticmethod
+    def _dev(t, cols, dtype="float32"):
+        if not (_is_device_tensor(t) and str(t.dtype).endswith(dtype) and t.is_contiguous()):
+            raise ValueError("expected a contiguous device tensor")
+        if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+            raise ValueError(f"expected {cols} columns")
+        return t.data_ptr()
+
+    def loss_grad(self, x, t):
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(lib().asp_mlp_loss_grad(self._n, self._dev(x, MLP_IN), self._dev(t, MLP_OUT),
+                                            int(x.shape[0]), ctypes.byref(loss), g.ctypes.data))
+        return loss.value, g
+
+    def train(self, x, t, order, batch: int, lr: float = 1e-3) -> float:
+        """Adam steps over the rows of x, t picked by `order` (device int32 tensor,
+        n_steps x batch indices); returns the mean batch loss."""
+        n_steps = int(order.numel()) // int(batch)
+        loss = ctypes.c_double()
+        self._check(lib().asp_mlp_train(self._n, self._dev(x, MLP_IN), self._dev(t, MLP_OUT),
+                                        int(x.shape[0]), self._dev(order, None, "int32"),
+                                        n_steps, int(batch), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def forward(self, x, y):
+        self._check(lib().asp_mlp_forward(self._n, self._dev(x, MLP_IN), int(x.shape[0]),
+                                          self._dev(y, MLP_OUT)))
+
+    def weights(self) -> np.ndarray:
+        w = np.zeros(MLP_PARAMS, dtype=np.float32)
+        self._check(lib().asp_mlp_weights(self._n, w.ctypes.data))
+        return w
 
 
 def report_dict(rep: FitReport) -> dict:
@@ -280,7 +410,8 @@ def report_dict(rep: FitReport) -> dict:
             "idx": rep.idx, "peak": rep.peak, "chi2_init": rep.chi2_init,
             "chi2_final": rep.chi2_final,
             "theta0": np.array(rep.theta0[: 4 * m]).reshape(-1, 4),
-            "theta": np.array(rep.theta[: 4 * m]).reshape(-1, 4), "fit_px": rep.fit_px}
+            "theta": np.array(rep.theta[: 4 * m]).reshape(-1, 4), "fit_px": rep.fit_px,
+            "init_source": rep.init_source, "init": np.array(rep.init[:4])}
 
 
 # The C names, for callers that prefer them.

@@ -36,11 +36,13 @@ struct DevState {
     int64_t forced_idx;            // >= 0: fit this pixel instead of the peak key
     int64_t idx;                   // pixel of the last fit
     float peak;                    // residual there before the fit
-    int32_t have_proposal;         // 1: proposal[] holds a learned initial value
-    double proposal[4];
+    int32_t have_proposal;         // 1 caller's proposal, 2 the network's, 0 none
+    double proposal[4];            // convolved-space (a, x, y, s), before clamping
     // report of the last fit
     int32_t n_active, lm_iters, converged, used_fallback;
     int32_t members[kMaxM];
+    int32_t init_source, pad2;     // have_proposal of the last fit
+    double init[4];                // its proposal
     double chi2_init, chi2_final;
     double theta0[kMaxN], theta[kMaxN];
     int64_t fit_px;
@@ -60,6 +62,8 @@ struct DevState {
     int32_t psf_status, pad1;
     // fit phase timers (device wall clock ticks) and event counts
     unsigned long long prof[kProfSlots];
+    // training-sample recording: slots filled
+    int64_t rec_n;
 };
 
 // State of one fit shared by the work-groups of the fit kernel.  The
@@ -97,6 +101,21 @@ struct Params {
     int32_t min_tiles;             // least tiles per work-group in a shared trial
     FitGlobal *fg;
     double *partials;              // fit_grid x kPartStride
+    // recording of (patch, target) training pairs; rec_cap = 0 disables
+    float *rec_patch;              // rec_cap x 1024
+    float *rec_target;             // rec_cap x 4
+    int32_t *rec_flag;             // rec_cap: 1 converged fit from the simple values
+    int64_t rec_cap;
+};
+
+// The proposal network in the layout of the inference kernel: W1 and W2
+// transposed (input-major) so that the threads of a work-group, one per
+// output unit, read consecutive addresses.
+constexpr int kNetIn = 1024, kNetH = 256, kNetOut = 4, kPatch = 32, kPatchHalf = 16;
+constexpr int64_t kNetParams = (int64_t)kNetH * kNetIn + kNetH + (int64_t)kNetH * kNetH + kNetH +
+                               (int64_t)kNetOut * kNetH + kNetOut;
+struct NetParams {
+    const float *w1t, *b1, *w2t, *b2, *w3, *b3;
 };
 
 // ---------------------------------------------------------------------------
@@ -145,6 +164,9 @@ hipError_t launch_psf_fit(const float *psf, int64_t Hp, int64_t Wp, double lobe_
                           DevState *st, int32_t *work, hipStream_t s);
 hipError_t launch_check_finite(const float *img, int64_t n, int32_t *flag, hipStream_t s);
 hipError_t launch_components(const Params &p, asp_component *out, hipStream_t s);
+hipError_t launch_propose(const Params &p, const NetParams &net, int use_net, hipStream_t s);
+hipError_t launch_sumsq(const float *img, int64_t n, double *part, int nblk, double *out,
+                        hipStream_t s);
 hipError_t fit_kernel_setup();
 int fit_grid_size(int device);
 

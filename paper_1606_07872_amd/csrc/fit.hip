@@ -68,6 +68,7 @@ struct WGShared {
     // selection scratch
     uint32_t mask[kT];
     double t0[4];
+    double sel[2];                 // peak pixel (x, y): the active set is selected around it
     int32_t nch, sel_done;
     // control
     unsigned long long tmark;      // phase timer mark (thread 0)
@@ -140,11 +141,13 @@ __device__ __forceinline__ bool spin_until(unsigned int *ctr, unsigned int targe
 
 // ---------------------------------------------------------------------------
 // Active set (the paper names the heuristic; its definition is in the 2004
-// paper).  Candidates: components whose amplitude has the new component's
-// sign and whose centre lies inside the new component's window, most recent
+// paper).  A function of the peak and the component list only: candidates are
+// components whose amplitude has the peak's sign and whose centre lies inside
+// the window of the simple start (the peak pixel, width omega_b), most recent
 // first; skip one closer than max(omega_b, min(s_j, s_m)) to a member already
-// taken (the new component first); at most K_max - 1.  FP64 products and sums
-// are rounded separately, so membership is reproducible bit for bit.
+// taken (the new component first, at the peak pixel with width omega_b); at
+// most K_max - 1.  FP64 products and sums are rounded separately, so
+// membership is reproducible bit for bit.
 // ---------------------------------------------------------------------------
 
 __device__ inline bool too_close(double xj, double yj, double sj, double xm, double ym,
@@ -160,7 +163,7 @@ __device__ inline bool too_close(double xj, double yj, double sj, double xm, dou
 __device__ __forceinline__ void consider(const Params &p, WGShared &S, int64_t j, double omega_b)
 {
     const double xj = p.cx[j], yj = p.cy[j], sj = p.cs[j];
-    if (too_close(xj, yj, sj, S.t0[1], S.t0[2], S.t0[3], omega_b)) return;
+    if (too_close(xj, yj, sj, S.sel[0], S.sel[1], omega_b, omega_b)) return;
     for (int u = 0; u < S.nch; ++u) {
         const int64_t mj = S.members[u + 1];
         if (too_close(xj, yj, sj, p.cx[mj], p.cy[mj], p.cs[mj], omega_b)) return;
@@ -184,7 +187,7 @@ __device__ __forceinline__ void setup_fit(const Params &p, FitGlobal *G, WGShare
         if (use_prop) {
             const double *q = p.st->proposal;
             t0[0] = q[0]; t0[1] = q[1]; t0[2] = q[2]; t0[3] = q[3];
-            if (!isfinite(t0[0])) t0[0] = pv;
+            if (!(t0[0] * pv > 0.0)) t0[0] = pv;     // the peak's sign; also NaN
             if (!(t0[1] >= (double)pc - 16.0)) t0[1] = (double)pc - 16.0;
             if (t0[1] > (double)pc + 16.0) t0[1] = (double)pc + 16.0;
             if (!(t0[2] >= (double)pr - 16.0)) t0[2] = (double)pr - 16.0;
@@ -198,12 +201,17 @@ __device__ __forceinline__ void setup_fit(const Params &p, FitGlobal *G, WGShare
         } else {
             t0[0] = pv; t0[1] = (double)pc; t0[2] = (double)pr; t0[3] = omega_b;
         }
-        make_window(t0[1], t0[2], halfwidth(t0[3], p.window_sigmas), p.H, p.W, S.win[0]);
+        // candidates: inside the simple start's window (peak pixel, omega_b),
+        // whatever the new component's start
+        S.sel[0] = (double)pc;
+        S.sel[1] = (double)pr;
+        make_window((double)pc, (double)pr, halfwidth(omega_b, p.window_sigmas), p.H, p.W,
+                    S.win[0]);
         S.nch = 0;
         S.sel_done = (p.max_active <= 1) ? 1 : 0;
     }
     __syncthreads();
-    const double a0 = S.t0[0];
+    const double a0 = S.peak;
     const int32_t b0 = S.win[0][0], b1 = S.win[0][1], b2 = S.win[0][2], b3 = S.win[0][3];
     const int64_t L = p.st->L;
     constexpr int64_t kSeg = (int64_t)kT * 32;
@@ -903,7 +911,21 @@ __device__ __forceinline__ void commit(const Params &p, WGShared &S)
         st->sum_trials += (unsigned long long)trials;
         st->not_converged += S.converged ? 0ull : 1ull;
         st->fallbacks += (unsigned long long)S.used_fallback;
+        st->init_source = S.use_prop ? st->have_proposal : 0;
+        for (int i = 0; i < 4; ++i) st->init[i] = S.use_prop ? st->proposal[i] : 0.0;
         st->have_proposal = 0;
+        if (p.rec_cap > 0 && st->rec_n < p.rec_cap) {
+            // the training pair of this iteration: the patch is already in place
+            const int64_t n = st->rec_n;
+            const int64_t r0 = S.idx / p.W, c0 = S.idx % p.W;
+            float *tg = p.rec_target + 4 * n;
+            tg[0] = (float)(S.th_c[0] / S.peak);
+            tg[1] = (float)log(S.th_c[3] / st->omega_b);
+            tg[2] = (float)(S.th_c[1] - (double)c0);
+            tg[3] = (float)(S.th_c[2] - (double)r0);
+            p.rec_flag[n] = S.converged | (S.used_fallback << 1) | (st->init_source << 2);
+            st->rec_n = n + 1;
+        }
         int nr = 0;
         int32_t bb[4] = {INT32_MAX, -1, INT32_MAX, -1};
         auto add_rect = [&](double a, double x, double y, double s, float sign) {

@@ -372,6 +372,47 @@ hipError_t launch_check_finite(const float *img, int64_t n, int32_t *flag, hipSt
     return hipGetLastError();
 }
 
+// Sum of squares of an image in FP64, in a fixed order: per-work-group
+// partials (grid-strided, float4), then one work-group sums them in order.
+__global__ __launch_bounds__(256) void k_sumsq_part(const float *__restrict__ img, int64_t n,
+                                                    double *part)
+{
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int64_t n4 = n >> 2;
+    const float4 *v4 = reinterpret_cast<const float4 *>(img);
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + t; i < n4;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float4 v = v4[i];
+        s += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+    }
+    if (blockIdx.x == 0 && t < (int)(n - 4 * n4)) s += (double)img[4 * n4 + t] * img[4 * n4 + t];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sumsq_final(const double *part, int n, double *out)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = s;
+}
+
+hipError_t launch_sumsq(const float *img, int64_t n, double *part, int nblk, double *out,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sumsq_part, dim3(nblk), dim3(256), 0, s, img, n, part);
+    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(64), 0, s, part, nblk, out);
+    return hipGetLastError();
+}
+
 // Eqs. 5-6: sky-plane parameters of every component.
 __global__ void k_components(Params p, asp_component *out)
 {

@@ -39,10 +39,18 @@ struct asp_ctx {
     bool timing = false;
     std::vector<hipEvent_t> events;       // 2 per launch slot
     std::vector<int> ev_kind;             // kind of each recorded pair
-    double t_ms[3] = {0.0, 0.0, 0.0};
-    int64_t t_n[3] = {0, 0, 0};
+    double t_ms[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t t_n[4] = {0, 0, 0, 0};
+    // the proposal network (input-major layout) and training-sample recording
+    float *net = nullptr;
+    asp::NetParams netp{};
+    double *sumsq = nullptr;              // 1024 partials + the total
     std::string err;
 };
+
+namespace asp {
+hipError_t launch_net_layout(const float *flat, float *net, hipStream_t s);
+}
 
 namespace {
 
@@ -74,7 +82,8 @@ void release(asp_ctx *c)
     (void)hipFree(c->ca); (void)hipFree(c->cx); (void)hipFree(c->cy); (void)hipFree(c->cs);
     (void)hipFree(c->c_added); (void)hipFree(c->c_updated);
     (void)hipFree(c->st); (void)hipFree(c->work); (void)hipFree(c->comp_out);
-    (void)hipFree(c->fg); (void)hipFree(c->partials);
+    (void)hipFree(c->fg); (void)hipFree(c->partials); (void)hipFree(c->net);
+    (void)hipFree(c->sumsq);
     if (c->st_host) (void)hipHostFree(c->st_host);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -268,9 +277,17 @@ asp_status harvest(asp_ctx *c)
     return ASP_OK;
 }
 
+bool use_net(const asp_ctx *c) { return c->opt.init_mode == 1 && c->net; }
+
 asp_status enqueue_iteration(asp_ctx *c)
 {
+    if (c->opt.init_mode == 1 && !c->net)
+        return fail(c, ASP_ERR_STATE, "learned start values need a network (asp_set_mlp)");
     asp_status s = timed(c, 0, [&] { return asp::launch_peak(c->P, c->peak_grid, c->stream); });
+    if (s == ASP_OK && (use_net(c) || c->P.rec_cap > 0))
+        s = timed(c, 3, [&] {
+            return asp::launch_propose(c->P, c->netp, use_net(c) ? 1 : 0, c->stream);
+        });
     if (s == ASP_OK) s = timed(c, 1, [&] { return asp::launch_fit(c->P, c->stream); });
     if (s == ASP_OK)
         s = timed(c, 2, [&] { return asp::launch_update(c->P, c->update_grid, c->stream); });
@@ -349,6 +366,8 @@ asp_status asp_fit_active_set(asp_ctx *c, int64_t idx, const asp_gauss *init,
     h->forced_idx = idx;
     HIP_OR_FAIL(c, hipMemcpyAsync((char *)c->st + offsetof(DevState, forced_idx), &h->forced_idx,
                                   sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    if (!init && c->opt.init_mode == 1 && !c->net)
+        return fail(c, ASP_ERR_STATE, "learned start values need a network (asp_set_mlp)");
     if (init) {
         h->have_proposal = 1;
         h->proposal[0] = init->amp; h->proposal[1] = init->x;
@@ -358,6 +377,9 @@ asp_status asp_fit_active_set(asp_ctx *c, int64_t idx, const asp_gauss *init,
                                       offsetof(DevState, n_active) - offsetof(DevState, have_proposal),
                                       hipMemcpyHostToDevice, c->stream));
     }
+    const bool net_start = !init && use_net(c);
+    if (net_start || c->P.rec_cap > 0)
+        HIP_OR_FAIL(c, asp::launch_propose(c->P, c->netp, net_start ? 1 : 0, c->stream));
     HIP_OR_FAIL(c, asp::launch_fit(c->P, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     asp_status s = pull_all(c);
@@ -380,6 +402,8 @@ asp_status asp_fit_active_set(asp_ctx *c, int64_t idx, const asp_gauss *init,
             rep->theta[i] = h->theta[i];
         }
         rep->fit_px = h->fit_px;
+        rep->init_source = h->init_source;
+        for (int i = 0; i < 4; ++i) rep->init[i] = h->init[i];
     }
     c->phase = 2;
     return h->converged ? ASP_OK : ASP_LM_NOT_CONVERGED;
@@ -505,6 +529,18 @@ asp_status asp_residual(asp_ctx *c, float *out)
     return ASP_OK;
 }
 
+asp_status asp_residual_sumsq(asp_ctx *c, double *sum_sq)
+{
+    if (!c || !sum_sq) return ASP_ERR_INVALID_ARG;
+    if (!c->sumsq) HIP_OR_FAIL(c, dev_alloc(&c->sumsq, 1025));
+    HIP_OR_FAIL(c, asp::launch_sumsq(c->R, c->H * c->W, c->sumsq, 1024, c->sumsq + 1024,
+                                     c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(sum_sq, c->sumsq + 1024, sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return ASP_OK;
+}
+
 asp_status asp_residual_device(asp_ctx *c, float **dev)
 {
     if (!c || !dev) return ASP_ERR_INVALID_ARG;
@@ -546,14 +582,68 @@ asp_status asp_kernel_timing(asp_ctx *c, int32_t on)
         if (s != ASP_OK) return s;
     }
     c->timing = on != 0;
-    for (int i = 0; i < 3; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
+    for (int i = 0; i < 4; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
     return ASP_OK;
 }
 
 asp_status asp_kernel_times(asp_ctx *c, double *ms, int64_t *launches, int32_t n)
 {
-    if (!c || n < 0 || n > 3 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
+    if (!c || n < 0 || n > 4 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i) { ms[i] = c->t_ms[i]; launches[i] = c->t_n[i]; }
+    return ASP_OK;
+}
+
+asp_status asp_set_mlp(asp_ctx *c, const float *weights, int64_t n)
+{
+    if (!c || !weights || n != asp::kNetParams) return ASP_ERR_INVALID_ARG;
+    float *flat = nullptr;
+    HIP_OR_FAIL(c, hipMalloc(&flat, sizeof(float) * asp::kNetParams));
+    hipError_t e = hipMemcpyAsync(flat, weights, sizeof(float) * asp::kNetParams,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && !c->net) e = hipMalloc(&c->net, sizeof(float) * asp::kNetParams);
+    if (e == hipSuccess) e = asp::launch_net_layout(flat, c->net, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(flat);
+    if (e != hipSuccess) return fail(c, ASP_ERR_DEVICE, std::string("asp_set_mlp: ") + hipGetErrorString(e));
+    const int64_t n1 = (int64_t)asp::kNetH * asp::kNetIn, n2 = (int64_t)asp::kNetH * asp::kNetH;
+    c->netp.w1t = c->net;
+    c->netp.b1 = c->net + n1;
+    c->netp.w2t = c->net + n1 + asp::kNetH;
+    c->netp.b2 = c->net + n1 + asp::kNetH + n2;
+    c->netp.w3 = c->net + n1 + 2 * asp::kNetH + n2;
+    c->netp.b3 = c->netp.w3 + (int64_t)asp::kNetOut * asp::kNetH;
+    return ASP_OK;
+}
+
+asp_status asp_set_init_mode(asp_ctx *c, int32_t mode)
+{
+    if (!c || mode < 0 || mode > 1) return ASP_ERR_INVALID_ARG;
+    if (mode == 1 && !c->net) return fail(c, ASP_ERR_STATE, "no network set (asp_set_mlp)");
+    c->opt.init_mode = mode;
+    return ASP_OK;
+}
+
+asp_status asp_record(asp_ctx *c, float *patches, float *targets, int32_t *flags, int64_t cap)
+{
+    if (!c || cap < 0 || (cap > 0 && (!patches || !targets || !flags))) return ASP_ERR_INVALID_ARG;
+    if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_record inside a step-API sequence");
+    c->P.rec_patch = cap > 0 ? patches : nullptr;
+    c->P.rec_target = cap > 0 ? targets : nullptr;
+    c->P.rec_flag = cap > 0 ? flags : nullptr;
+    c->P.rec_cap = cap;
+    c->st_host->rec_n = 0;
+    HIP_OR_FAIL(c, hipMemcpyAsync((char *)c->st + offsetof(DevState, rec_n), &c->st_host->rec_n,
+                                  sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return ASP_OK;
+}
+
+asp_status asp_record_count(asp_ctx *c, int64_t *n)
+{
+    if (!c || !n) return ASP_ERR_INVALID_ARG;
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    *n = c->st_host->rec_n;
     return ASP_OK;
 }
 

@@ -343,3 +343,28 @@ def test_active_set_rule(orc):
     o.load_state(img, comps[:5], 5)
     rep = o.step()
     assert rep["members"] == [-1, 4, 0]
+
+
+def test_active_set_ignores_the_proposal(orc):
+    """The active set is a function of the peak and the component list: the same
+    hand-built case started from a wide, offset proposal selects the same
+    members as from the simple values, and a proposal of the wrong sign starts
+    from the peak value."""
+    H = W = 64
+    img = np.zeros((H, W))
+    img[30, 30] = 1.0
+    comps = np.array([
+        [0.5, 33.0, 30.0, 2.0],
+        [0.5, 30.0, 25.0, 3.0],
+        [0.5, 26.0, 34.0, 1.6],
+        [0.5, 45.0, 30.0, 2.0],    # outside the simple start's window, inside a wide one
+    ])
+    o = orc.Oracle(img, gain=0.1, max_iter=10, max_active=5, alpha_b=1.0, omega_b=1.5)
+    o.load_state(img, comps, 4)
+    plain = o.step()
+    o.load_state(img, comps, 4)
+    wide = o.step(init=[1.0, 36.0, 30.0, 6.0])
+    assert plain["members"] == wide["members"] == [-1, 2, 1, 0]
+    o.load_state(img, comps, 4)
+    flipped = o.step(init=[-1.0, 30.0, 30.0, 1.5])
+    assert flipped["theta0"][0][0] == 1.0
