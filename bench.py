@@ -86,6 +86,52 @@ def cpu_baseline(f, R0, comps0, k0, alpha_b, omega_b, seconds):
                       "one thread"}
 
 
+def learned_vs_plain(args, f, wpath, rep, secs, rms_plain, torch, asp):
+    """Time to the plain run's residual RMS with the network's start values.
+    A second context warms up plainly over the same iterations, then runs in
+    learned mode in chunks of 100 iterations (an RMS check on the device after
+    each) until its residual RMS is at most the plain run's, or 3x the plain
+    run's iterations have passed."""
+    import numpy as np
+    w = np.load(wpath)
+    d_dirty = torch.from_numpy(f.dirty).cuda()
+    d_psf = torch.from_numpy(f.psf).cuda()
+    total = args.warmup + 3 * args.steps
+    ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=max(f.max_iter, total),
+                      max_active=f.max_active, fit_solo_tiles=args.solo_tiles,
+                      fit_min_tiles=args.min_tiles)
+    del d_dirty, d_psf
+    ctx.set_mlp(w)
+    ctx.run(args.warmup)
+    ctx.set_init_mode(1)
+    torch.cuda.synchronize()
+    done, trials, fallbacks, t_learned = 0, 0, 0, 0.0
+    rms = ctx.residual_rms()
+    reached = False
+    while done < 3 * rep["iterations"]:
+        t0 = time.perf_counter()
+        rc, r = ctx.run(100)
+        torch.cuda.synchronize()
+        t_learned += time.perf_counter() - t0
+        done += r["iterations"]
+        trials += r["lm_trials"]
+        fallbacks += r["fallbacks"]
+        rms = ctx.residual_rms()
+        if rms <= rms_plain or r["iterations"] == 0:
+            reached = rms <= rms_plain
+            break
+    ctx.close()
+    out = {"weights": os.path.basename(wpath),
+           "plain": {"iterations": rep["iterations"], "seconds": secs, "rms": rms_plain,
+                     "trials_per_fit": rep["lm_trials"] / max(rep["iterations"], 1)},
+           "learned": {"iterations": done, "seconds": t_learned, "rms": rms,
+                       "trials_per_fit": trials / max(done, 1), "fallbacks": fallbacks},
+           "reached_plain_rms": reached,
+           "time_ratio_learned_over_plain": (t_learned / secs) if reached and secs > 0 else None}
+    log(f"learned vs plain {json.dumps(out)}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +146,9 @@ def main():
     ap.add_argument("--min-tiles", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM counters)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-versus-plain start comparison")
+    ap.add_argument("--weights", default=None, help="proposal network weights (.npy)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the minor cycle "
@@ -191,6 +240,12 @@ def main():
             hbm["k_update"] = {"achieved_gbs": gbs, "frac": gbs / PEAK_HBM_GBS,
                                "avg_launch_us": upd_ms / upd_n * 1e3, "bytes_per_launch": b}
 
+    rms_plain = ctx.residual_rms()
+    learned = None
+    wpath = args.weights or os.path.join(ROOT, "paper_1606_07872_amd", "proposal_weights.npy")
+    if not args.no_learned and os.path.exists(wpath):
+        learned = learned_vs_plain(args, f, wpath, rep, secs, rms_plain, torch, asp)
+
     cpu = None
     if want_cpu:
         log(f"oracle baseline for {args.cpu_seconds:.0f}s from iteration {k0}")
@@ -216,6 +271,7 @@ def main():
                    "kernel_events": not args.no_kernel_events},
         "roofline": roofline,
         "hbm": hbm,
+        "learned_vs_plain": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

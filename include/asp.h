@@ -92,9 +92,10 @@ typedef struct {
     double theta0[4 * ASP_MAX_ACTIVE];   /* start (a, x, y, s) per member        */
     double theta[4 * ASP_MAX_ACTIVE];    /* fitted, before the loop gain         */
     int64_t fit_px;              /* pixels in the union of windows at the fit    */
-    int32_t init_source;         /* start of the new component: 0 simple values,
+    int32_t init_source;         /* proposal considered: 0 none (simple values),
                                     1 the caller's init, 2 the network           */
-    int32_t pad2;
+    int32_t start_from_proposal; /* 1: the proposal scored a lower objective than
+                                    the simple values and LM started from it     */
     double init[4];              /* the proposal (a, x, y, s) before clamping     */
 } asp_fit_report;
 
@@ -168,10 +169,14 @@ asp_status asp_find_peak(asp_ctx *ctx, int64_t *idx, float *value);
 /*
  * Step 3 (Sect. 3, Eq. 4): select the active set around pixel idx and fit it
  * by LM on the device.  init = NULL uses the simple initial values (the
- * residual at idx and the main-lobe width); otherwise it is a proposal in
- * convolved space (clamped to s >= omega_b and to 16 px of the peak), with
- * the simple values as fallback if its fit does not converge.  Must follow
- * asp_find_peak.  rep may be NULL.  Returns ASP_OK or ASP_LM_NOT_CONVERGED.
+ * residual at idx and the main-lobe width), or the network's proposal in
+ * learned mode; otherwise init is a proposal in convolved space (clamped to
+ * the peak's sign, s >= omega_b and 16 px of the peak).  With a proposal the
+ * objective is evaluated at it and at the simple values and LM starts from the
+ * lower; if it started from the proposal and does not converge, the simple
+ * values are fitted instead.  The active set depends on idx and the component
+ * list only.  Must follow asp_find_peak.  rep may be NULL.  Returns ASP_OK or
+ * ASP_LM_NOT_CONVERGED.
  */
 asp_status asp_fit_active_set(asp_ctx *ctx, int64_t idx, const asp_gauss *init,
                               asp_fit_report *rep);

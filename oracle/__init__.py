@@ -58,7 +58,7 @@ class _Report(ctypes.Structure):
                 ("idx", ctypes.c_int64), ("peak", ctypes.c_double),
                 ("members", ctypes.c_int32 * MAX_ACTIVE),
                 ("lm_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("used_fallback", ctypes.c_int32), ("pad2", ctypes.c_int32),
+                ("used_fallback", ctypes.c_int32), ("start_from_proposal", ctypes.c_int32),
                 ("chi2_init", ctypes.c_double), ("chi2_final", ctypes.c_double),
                 ("theta", ctypes.c_double * (4 * MAX_ACTIVE)),
                 ("theta0", ctypes.c_double * (4 * MAX_ACTIVE)),
@@ -249,6 +249,7 @@ class Oracle:
         out = {"status": rc, "idx": int(rep.idx), "peak": rep.peak, "n_active": m,
                "members": list(rep.members[:m]), "lm_iters": rep.lm_iters,
                "converged": bool(rep.converged), "used_fallback": bool(rep.used_fallback),
+               "start_from_proposal": bool(rep.start_from_proposal),
                "chi2_init": rep.chi2_init, "chi2_final": rep.chi2_final,
                "theta": np.array(rep.theta[: 4 * m]).reshape(-1, 4),
                "theta0": np.array(rep.theta0[: 4 * m]).reshape(-1, 4),

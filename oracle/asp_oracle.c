@@ -482,12 +482,12 @@ int orc_psf_fit(const double *psf, int64_t Hp, int64_t Wp, double main_lobe_frac
 /* the 2004 paper, which is not available).  Reading: candidates are         */
 /* existing components whose amplitude has the sign of the peak (zero       */
 /* excluded) and whose centre lies inside the window of the simple start    */
-/* (peak pixel, omega_b) whatever the new component's start value, so the   */
-/* set depends on the peak and the component list only; they are            */
+/* (peak pixel, omega_b) whatever the new component's start value; they are */
 /* taken most recent first up to K_max - 1 (with the sign bounds of the fit, */
 /* no two members can cancel each other); a                                  */
 /* candidate is skipped when it is too close to a member already taken (the */
-/* new component first): centres closer than                                 */
+/* new component first, at the simple start and, with a proposal, at the   */
+/* proposal too): centres closer than                                        */
 /* max(omega_b, min(s_j, s_m)), where two Gaussians of similar place and     */
 /* width would make the joint fit degenerate.  Only FP64 products, sums,     */
 /* min/max and compares of stored values: reproducible bit for bit.          */
@@ -503,7 +503,7 @@ static int too_close(double xj, double yj, double sj, double xm, double ym, doub
 }
 
 static int select_active(const orc_state *st, const double *t0, const int64_t bnew[4],
-                         int32_t *chosen)
+                         const double *prop4, int32_t *chosen)
 {
     int nch = 0;
     for (int64_t j = st->L - 1; j >= 0 && nch < st->max_active - 1; --j) {
@@ -512,6 +512,9 @@ static int select_active(const orc_state *st, const double *t0, const int64_t bn
         if (!(cj->y >= (double)bnew[0] && cj->y <= (double)bnew[1] &&
               cj->x >= (double)bnew[2] && cj->x <= (double)bnew[3])) continue;
         if (too_close(cj->x, cj->y, cj->s, t0[1], t0[2], t0[3], st->omega_b)) continue;
+        /* a proposal start is a second place of the new component */
+        if (prop4 && too_close(cj->x, cj->y, cj->s, prop4[1], prop4[2], prop4[3], st->omega_b))
+            continue;
         int close = 0;
         for (int u = 0; u < nch && !close; ++u) {
             const orc_comp *cm = &st->comps[chosen[u]];
@@ -559,16 +562,22 @@ static void set_bounds(fit_problem *fp, const double *theta)
 
 /* The active set depends on the peak and the component list only: it is
  * selected around the simple start `sel` (peak value, peak pixel, omega_b)
- * whatever the start `init4` of the new component. */
+ * whatever the start `init4` of the new component.
+ * With a proposal `prop4` (NULL for none) the new component has two starts,
+ * the simple values init4 and the proposal; its centre bounds are the hull of
+ * the two start windows, the objective is evaluated at both, and LM starts
+ * from the lower one (the simple values on a tie).  *won = 1 when that is the
+ * proposal. */
 static int fit_from(const orc_state *st, const double *init4, const double *sel,
-                    orc_report *rep, double *theta, lm_result *out, double *hess_out)
+                    const double *prop4, int *won, orc_report *rep, double *theta,
+                    lm_result *out, double *hess_out)
 {
     double t0[4];
     memcpy(t0, init4, sizeof t0);
     int64_t wsel[4];
     comp_window(st, sel[1], sel[2], sel[3], wsel);
     int32_t chosen[ORC_MAX_ACTIVE];
-    int nch = select_active(st, sel, wsel, chosen);
+    int nch = select_active(st, sel, wsel, prop4, chosen);
     fit_problem fp;
     memset(&fp, 0, sizeof fp);
     fp.st = st;
@@ -585,8 +594,29 @@ static int fit_from(const orc_state *st, const double *init4, const double *sel,
         comp_window(st, t[1], t[2], t[3], fp.wold[u + 1]);
     }
     rep->n_active = fp.m;
-    memcpy(rep->theta0, theta, sizeof(double) * 4 * (size_t)fp.m);
     set_bounds(&fp, theta);
+    if (won) *won = 0;
+    if (prop4) {
+        int64_t wp[4];
+        comp_window(st, prop4[1], prop4[2], prop4[3], wp);
+        if ((double)wp[2] < fp.lo[1]) fp.lo[1] = (double)wp[2];
+        if ((double)wp[3] > fp.hi[1]) fp.hi[1] = (double)wp[3];
+        if ((double)wp[0] < fp.lo[2]) fp.lo[2] = (double)wp[0];
+        if ((double)wp[1] > fp.hi[2]) fp.hi[2] = (double)wp[1];
+        double alt[4 * ORC_MAX_ACTIVE];
+        memcpy(alt, theta, sizeof(double) * 4 * (size_t)fp.m);
+        memcpy(alt, prop4, 4 * sizeof(double));
+        clip_to(alt, 4 * fp.m, fp.lo, fp.hi);
+        clip_to(theta, 4 * fp.m, fp.lo, fp.hi);
+        double Fs = fit_eval(&fp, theta, NULL, NULL, NULL, NULL);
+        double Fp = fit_eval(&fp, alt, NULL, NULL, NULL, NULL);
+        if (!isfinite(Fs)) Fs = INFINITY;
+        if (Fp < Fs) {
+            memcpy(theta, alt, sizeof(double) * 4 * (size_t)fp.m);
+            if (won) *won = 1;
+        }
+    }
+    memcpy(rep->theta0, theta, sizeof(double) * 4 * (size_t)fp.m);
     *out = lm_fit(&fp, theta, st->lm_max_iter, st->lm_mu0, st->lm_tol, hess_out);
     rep->omega_px = out->npx;
     return ORC_OK;
@@ -636,18 +666,20 @@ int orc_step(orc_state *st, const double *init, orc_report *rep, double *hess_ou
         if (p4[2] > (double)(st->H - 1)) p4[2] = (double)(st->H - 1);
         if (!(p4[3] >= st->omega_b)) p4[3] = st->omega_b;
         if (p4[3] > width_max(st)) p4[3] = width_max(st);
-        rc = fit_from(st, p4, plain, rep, theta, &lmr, hess_out);
+        int won = 0;
+        rc = fit_from(st, plain, plain, p4, &won, rep, theta, &lmr, hess_out);
         if (rc != ORC_OK) return rep->status = rc;
-        if (!lmr.converged) {
+        rep->start_from_proposal = won;
+        if (won && !lmr.converged) {
             /* The simple initial values are the fallback. */
             used_fallback = 1;
             int tr = lmr.trials;
-            rc = fit_from(st, plain, plain, rep, theta, &lmr, hess_out);
+            rc = fit_from(st, plain, plain, NULL, NULL, rep, theta, &lmr, hess_out);
             if (rc != ORC_OK) return rep->status = rc;
             lmr.trials += tr;
         }
     } else {
-        rc = fit_from(st, plain, plain, rep, theta, &lmr, hess_out);
+        rc = fit_from(st, plain, plain, NULL, NULL, rep, theta, &lmr, hess_out);
         if (rc != ORC_OK) return rep->status = rc;
     }
     int m = rep->n_active;

@@ -63,7 +63,8 @@ typedef struct {
     int64_t idx;                /* peak pixel                                 */
     double peak;                /* R[idx] before the step                     */
     int32_t members[ORC_MAX_ACTIVE];  /* -1 = the new component, else index   */
-    int32_t lm_iters, converged, used_fallback, pad2;
+    int32_t lm_iters, converged, used_fallback;
+    int32_t start_from_proposal; /* LM started from the proposal (it scored lower) */
     double chi2_init, chi2_final;
     double theta[4 * ORC_MAX_ACTIVE]; /* fitted (a,x,y,s) per member, pre-gain */
     double theta0[4 * ORC_MAX_ACTIVE];/* starting point of the fit            */

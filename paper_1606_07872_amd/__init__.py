@@ -72,7 +72,7 @@ class FitReport(ctypes.Structure):
                 ("theta0", ctypes.c_double * (4 * MAX_ACTIVE)),
                 ("theta", ctypes.c_double * (4 * MAX_ACTIVE)),
                 ("fit_px", ctypes.c_int64), ("init_source", ctypes.c_int32),
-                ("pad2", ctypes.c_int32), ("init", ctypes.c_double * 4)]
+                ("start_from_proposal", ctypes.c_int32), ("init", ctypes.c_double * 4)]
 
 
 class RunReport(ctypes.Structure):
@@ -411,7 +411,8 @@ def report_dict(rep: FitReport) -> dict:
             "chi2_final": rep.chi2_final,
             "theta0": np.array(rep.theta0[: 4 * m]).reshape(-1, 4),
             "theta": np.array(rep.theta[: 4 * m]).reshape(-1, 4), "fit_px": rep.fit_px,
-            "init_source": rep.init_source, "init": np.array(rep.init[:4])}
+            "init_source": rep.init_source, "init": np.array(rep.init[:4]),
+            "start_from_proposal": bool(rep.start_from_proposal)}
 
 
 # The C names, for callers that prefer them.

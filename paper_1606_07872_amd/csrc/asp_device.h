@@ -41,7 +41,8 @@ struct DevState {
     // report of the last fit
     int32_t n_active, lm_iters, converged, used_fallback;
     int32_t members[kMaxM];
-    int32_t init_source, pad2;     // have_proposal of the last fit
+    int32_t init_source;           // have_proposal of the last fit
+    int32_t start_prop;            // its LM started from the proposal
     double init[4];                // its proposal
     double chi2_init, chi2_final;
     double theta0[kMaxN], theta[kMaxN];

@@ -67,7 +67,9 @@ struct WGShared {
     int64_t idx, npx_c;
     // selection scratch
     uint32_t mask[kT];
-    double t0[4];
+    double t0[4];                  // the simple start of the new component
+    double alt[4];                 // a proposal start, compared with t0 by the objective
+    int32_t alt_pending, chose_prop;
     double sel[2];                 // peak pixel (x, y): the active set is selected around it
     int32_t nch, sel_done;
     // control
@@ -141,13 +143,13 @@ __device__ __forceinline__ bool spin_until(unsigned int *ctr, unsigned int targe
 
 // ---------------------------------------------------------------------------
 // Active set (the paper names the heuristic; its definition is in the 2004
-// paper).  A function of the peak and the component list only: candidates are
-// components whose amplitude has the peak's sign and whose centre lies inside
-// the window of the simple start (the peak pixel, width omega_b), most recent
-// first; skip one closer than max(omega_b, min(s_j, s_m)) to a member already
-// taken (the new component first, at the peak pixel with width omega_b); at
-// most K_max - 1.  FP64 products and sums are rounded separately, so
-// membership is reproducible bit for bit.
+// paper).  Candidates are components whose amplitude has the peak's sign and
+// whose centre lies inside the window of the simple start (the peak pixel,
+// width omega_b), most recent first; skip one closer than
+// max(omega_b, min(s_j, s_m)) to a member already taken (the new component
+// first: at the peak pixel with width omega_b and, with a proposal, at the
+// proposal too); at most K_max - 1.  FP64 products and sums are rounded
+// separately, so membership is reproducible bit for bit.
 // ---------------------------------------------------------------------------
 
 __device__ inline bool too_close(double xj, double yj, double sj, double xm, double ym,
@@ -164,6 +166,8 @@ __device__ __forceinline__ void consider(const Params &p, WGShared &S, int64_t j
 {
     const double xj = p.cx[j], yj = p.cy[j], sj = p.cs[j];
     if (too_close(xj, yj, sj, S.sel[0], S.sel[1], omega_b, omega_b)) return;
+    // a proposal start is a second place of the new component
+    if (S.alt_pending && too_close(xj, yj, sj, S.alt[1], S.alt[2], S.alt[3], omega_b)) return;
     for (int u = 0; u < S.nch; ++u) {
         const int64_t mj = S.members[u + 1];
         if (too_close(xj, yj, sj, p.cx[mj], p.cy[mj], p.cs[mj], omega_b)) return;
@@ -184,22 +188,26 @@ __device__ __forceinline__ void setup_fit(const Params &p, FitGlobal *G, WGShare
         const double pv = S.peak;
         double *t0 = S.t0;
         const double cap = width_cap(p);
+        t0[0] = pv; t0[1] = (double)pc; t0[2] = (double)pr; t0[3] = omega_b;
+        S.alt_pending = use_prop ? 1 : 0;
+        S.chose_prop = 0;
         if (use_prop) {
+            // the proposal, clamped: the peak's sign, within 16 px of the peak
+            // and inside the image, omega_b <= s <= the width cap
             const double *q = p.st->proposal;
-            t0[0] = q[0]; t0[1] = q[1]; t0[2] = q[2]; t0[3] = q[3];
-            if (!(t0[0] * pv > 0.0)) t0[0] = pv;     // the peak's sign; also NaN
-            if (!(t0[1] >= (double)pc - 16.0)) t0[1] = (double)pc - 16.0;
-            if (t0[1] > (double)pc + 16.0) t0[1] = (double)pc + 16.0;
-            if (!(t0[2] >= (double)pr - 16.0)) t0[2] = (double)pr - 16.0;
-            if (t0[2] > (double)pr + 16.0) t0[2] = (double)pr + 16.0;
-            if (t0[1] < 0.0) t0[1] = 0.0;
-            if (t0[1] > (double)(p.W - 1)) t0[1] = (double)(p.W - 1);
-            if (t0[2] < 0.0) t0[2] = 0.0;
-            if (t0[2] > (double)(p.H - 1)) t0[2] = (double)(p.H - 1);
-            if (!(t0[3] >= omega_b)) t0[3] = omega_b;
-            if (t0[3] > cap) t0[3] = cap;
-        } else {
-            t0[0] = pv; t0[1] = (double)pc; t0[2] = (double)pr; t0[3] = omega_b;
+            double *a = S.alt;
+            a[0] = q[0]; a[1] = q[1]; a[2] = q[2]; a[3] = q[3];
+            if (!(a[0] * pv > 0.0)) a[0] = pv;     // also NaN
+            if (!(a[1] >= (double)pc - 16.0)) a[1] = (double)pc - 16.0;
+            if (a[1] > (double)pc + 16.0) a[1] = (double)pc + 16.0;
+            if (!(a[2] >= (double)pr - 16.0)) a[2] = (double)pr - 16.0;
+            if (a[2] > (double)pr + 16.0) a[2] = (double)pr + 16.0;
+            if (a[1] < 0.0) a[1] = 0.0;
+            if (a[1] > (double)(p.W - 1)) a[1] = (double)(p.W - 1);
+            if (a[2] < 0.0) a[2] = 0.0;
+            if (a[2] > (double)(p.H - 1)) a[2] = (double)(p.H - 1);
+            if (!(a[3] >= omega_b)) a[3] = omega_b;
+            if (a[3] > cap) a[3] = cap;
         }
         // candidates: inside the simple start's window (peak pixel, omega_b),
         // whatever the new component's start
@@ -277,6 +285,15 @@ __device__ __forceinline__ void setup_fit(const Params &p, FitGlobal *G, WGShare
         }
         int32_t w[4];
         make_window(th[1], th[2], halfwidth(th[3], p.window_sigmas), p.H, p.W, w);
+        if (t == 0 && S.alt_pending) {
+            // two starts: the centre may range over the hull of both windows
+            int32_t wa[4];
+            make_window(S.alt[1], S.alt[2], halfwidth(S.alt[3], p.window_sigmas), p.H, p.W, wa);
+            w[0] = wa[0] < w[0] ? wa[0] : w[0];
+            w[1] = wa[1] > w[1] ? wa[1] : w[1];
+            w[2] = wa[2] < w[2] ? wa[2] : w[2];
+            w[3] = wa[3] > w[3] ? wa[3] : w[3];
+        }
         // bounds: the start sign of the amplitude; the centre inside its start
         // window; omega_b <= s <= the width cap
         const bool neg = th[0] < 0.0;
@@ -694,6 +711,20 @@ __device__ __forceinline__ void lm_accept(const Params &p, WGShared &S)
         S.trials = 0;
         S.converged = 0;
         S.chi2_init = S.chi2e;
+        S.phase = S.alt_pending ? 2 : 1;
+        return;
+    }
+    if (S.phase == 2) {
+        // the proposal against the simple start: the lower objective is the
+        // start of LM; the damping is untouched
+        double Fp = S.Fe;
+        if (!isfinite(Fp)) Fp = INFINITY;
+        S.accept = (Fp < S.F_c) ? 1 : 0;
+        S.chose_prop = S.accept;
+        if (S.accept) {
+            S.chi2_init = S.chi2e;
+            for (int i = 0; i < 4; ++i) S.th0[i] = S.th_e[i];
+        }
         S.phase = 1;
         return;
     }
@@ -822,6 +853,29 @@ __device__ __forceinline__ void lm_step(const Params &p, WGShared &S, double *He
     const int t = threadIdx.x;
     const int n = S.n;
     if (t == 0) lm_accept(p, S);
+    __syncthreads();
+    if (S.phase == 2) {
+        // the simple start is evaluated (and accepted); the next evaluation
+        // is the proposal start with the other members unchanged
+        for (int e = t; e < n * n; e += kT) Hc[e] = He[e];
+        if (t < n) {
+            S.th_c[t] = S.th_e[t];
+            S.g_c[t] = S.ge[t];
+            if (t < 4) {
+                double v = S.alt[t];
+                if (!(v >= S.lo[t])) v = S.lo[t];
+                if (v > S.hi[t]) v = S.hi[t];
+                S.th_e[t] = v;
+            }
+        }
+        if (t == 0) {
+            S.F_c = S.Fe; S.chi2_c = S.chi2e; S.npx_c = S.npx_e;
+            S.alt_pending = 0;
+            S.finished = 0;
+        }
+        __syncthreads();
+        return;
+    }
     if (n <= 8) {
         if (t == 0) {
             if (n == 4) lm_solve_small<4>(p.lm_max_iter, S, He, Hc);
@@ -912,6 +966,7 @@ __device__ __forceinline__ void commit(const Params &p, WGShared &S)
         st->not_converged += S.converged ? 0ull : 1ull;
         st->fallbacks += (unsigned long long)S.used_fallback;
         st->init_source = S.use_prop ? st->have_proposal : 0;
+        st->start_prop = S.chose_prop && !S.used_fallback;
         for (int i = 0; i < 4; ++i) st->init[i] = S.use_prop ? st->proposal[i] : 0.0;
         st->have_proposal = 0;
         if (p.rec_cap > 0 && st->rec_n < p.rec_cap) {
@@ -1149,7 +1204,7 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
             atomicAdd(&st->prof[kPEvalPx], npx);
         }
         if (!S.finished) continue;
-        if (S.use_prop && !S.converged && S.pass == 0) {
+        if (S.use_prop && S.chose_prop && !S.converged && S.pass == 0) {
             // the learned start did not converge: the simple values instead
             if (t == 0) {
                 S.trials_total += S.trials;

@@ -403,6 +403,7 @@ asp_status asp_fit_active_set(asp_ctx *c, int64_t idx, const asp_gauss *init,
         }
         rep->fit_px = h->fit_px;
         rep->init_source = h->init_source;
+        rep->start_from_proposal = h->start_prop;
         for (int i = 0; i < 4; ++i) rep->init[i] = h->init[i];
     }
     c->phase = 2;

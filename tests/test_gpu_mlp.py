@@ -171,6 +171,7 @@ def test_lockstep_from_network_start():
         orep = orc.step(init=rep["init"])
         assert orep["idx"] == idx
         assert orep["members"] == rep["members"], (it, orep["members"], rep["members"])
+        assert orep["start_from_proposal"] == rep["start_from_proposal"], it
         assert orep["used_fallback"] == rep["used_fallback"] or not (orep["converged"] and rep["converged"])
         R1 = ctx.residual().astype(np.float64)
         assert np.abs(R1 - orc.R).max() <= RESID_TOL * peak
@@ -209,4 +210,46 @@ def test_recorded_pairs_match_oracle():
         np.testing.assert_allclose(T[n], want_t, rtol=1e-6, atol=1e-6)
         assert F[n] == (int(rep["converged"]) | (int(rep["used_fallback"]) << 1))
     ctx.record(None, None, None)
+    ctx.close()
+
+
+def test_trained_network_cuts_lm_trials():
+    """What the trained network gains over the simple values.  Training pairs
+    are recorded on the device from plain runs of six 1024 x 1024 fields and
+    the network is trained by the library's kernels; then, on a held-out field
+    run in learned mode, every pre-step state is fitted by the oracle twice --
+    from the simple values and from the device's proposal -- so both fits see
+    the identical problem.  The learned start must need clearly fewer LM trials
+    and, where the fit is not degenerate, reach the same component."""
+    from paper_1606_07872_amd import proposal
+    fields = [skygen.make_c1024(1001 + i) for i in range(6)]
+    X, T = proposal.record_fields(fields, 1500, torch)
+    print("training pairs", X.shape[0], flush=True)
+    w, losses, val = proposal.train(X, T, 20, 256, 1e-3, 1, torch)
+    print("losses", losses[0], losses[-1], "validation", val, flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+    f = skygen.make_c1024(1000)
+    ctx = learned_ctx(f, w)
+    ab, wb = ctx.psf_gauss()
+    orc = oracle.Oracle(f.dirty, gain=f.gain, threshold=f.threshold, max_iter=f.max_iter,
+                        max_active=f.max_active, alpha_b=ab, omega_b=wb, cap=f.max_iter + 1)
+    tr_plain, tr_learned, same = [], [], 0
+    for it in range(30):
+        R0 = ctx.residual()
+        comps0 = ctx.components_raw()
+        k0, _ = ctx.counts()
+        rc, idx, val = ctx.find_peak()
+        rc, rep = ctx.fit_active_set(idx)
+        ctx.update_residual()
+        orc.load_state(R0, comps0, k0)
+        p = orc.step()
+        orc.load_state(R0, comps0, k0)
+        q = orc.step(init=rep["init"])
+        tr_plain.append(p["lm_iters"])
+        tr_learned.append(q["lm_iters"])
+        same += bool(np.all(param_errors(p["theta"][:1], q["theta"][:1]) <= 1.0))
+    print("mean trials plain", np.mean(tr_plain), "learned", np.mean(tr_learned), "same", same,
+          flush=True)
+    assert np.mean(tr_learned) <= 0.8 * np.mean(tr_plain)
+    assert same >= 15
     ctx.close()
