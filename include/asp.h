@@ -296,6 +296,51 @@ asp_status asp_mlp_train(asp_mlp *net, const float *x_dev, const float *t_dev, i
 asp_status asp_mlp_forward(asp_mlp *net, const float *x_dev, int64_t rows, float *y_dev);
 asp_status asp_mlp_weights(asp_mlp *net, float *out);
 
+/*
+ * Batched fields: many independent fields deconvolved by one persistent
+ * launch, captured in a HIP graph and replayed.  Each field is an ordinary
+ * context (asp_batch_field; every single-field call works on it between
+ * runs); its minor cycle is the one of asp_run.  The launch fills the GPU
+ * with work-groups grouped in teams of team_size on one XCD each; a team takes
+ * fields from a queue (largest first) and runs each for n_iter iterations or
+ * until it stops.
+ *   asp_batch_create   fields i = 0..n_fields-1 from host arrays, as
+ *                      asp_create with gain[i], threshold[i]; opt (NULL =
+ *                      defaults) applies to all; opt->stream must be NULL.
+ *   asp_batch_config   team_size (work-groups per team; must divide the
+ *                      work-groups of one XCD), solo_tiles, min_tiles as in
+ *                      asp_options; 0 keeps a value.
+ *   asp_batch_run      one launch: up to n_iter iterations per field.  rep:
+ *                      iterations summed over fields, fields stopped, fields
+ *                      failed, device milliseconds of the launch.
+ *   asp_batch_autotune coordinate search over team size, solo_tiles and
+ *                      min_tiles on real chunks of probe_iter iterations per
+ *                      field (the fields advance); applies and returns the
+ *                      fastest.
+ * A batch is not thread-safe; its contexts must not be used while it runs.
+ */
+typedef struct asp_batch asp_batch;
+typedef struct {
+    int64_t iterations;
+    int64_t fields_stopped;
+    int64_t fields_failed;
+    double ms;
+} asp_batch_report;
+asp_status asp_batch_create(int32_t n_fields, const float *const *dirty, const int64_t *H,
+                            const int64_t *W, const float *const *psf, const int64_t *Hp,
+                            const int64_t *Wp, const float *gain, const float *threshold,
+                            const asp_options *opt, asp_batch **out);
+void asp_batch_destroy(asp_batch *batch);
+const char *asp_batch_last_error(const asp_batch *batch);
+asp_status asp_batch_field(asp_batch *batch, int32_t i, asp_ctx **ctx);
+asp_status asp_batch_config(asp_batch *batch, int32_t team_size, int32_t solo_tiles,
+                            int32_t min_tiles);
+asp_status asp_batch_get_config(asp_batch *batch, int32_t *team_size, int32_t *solo_tiles,
+                                int32_t *min_tiles, int32_t *grid);
+asp_status asp_batch_run(asp_batch *batch, int64_t n_iter, asp_batch_report *rep);
+asp_status asp_batch_autotune(asp_batch *batch, int64_t probe_iter, int32_t *team_size,
+                              int32_t *solo_tiles, int32_t *min_tiles);
+
 /* Diagnostics: per-kernel device time.  With timing on, asp_run and asp_step
  * record a HIP event pair on the context's stream around every launch they
  * make (which adds two event packets per launch); asp_kernel_times returns the

@@ -27,7 +27,9 @@ EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destro
            "asp_kernel_timing", "asp_kernel_times", "asp_set_mlp", "asp_set_init_mode",
            "asp_record", "asp_record_count", "asp_mlp_create", "asp_mlp_destroy",
            "asp_mlp_last_error", "asp_mlp_loss_grad", "asp_mlp_train", "asp_mlp_forward",
-           "asp_mlp_weights", "asp_residual_sumsq"]
+           "asp_mlp_weights", "asp_residual_sumsq", "asp_batch_create", "asp_batch_destroy",
+           "asp_batch_last_error", "asp_batch_field", "asp_batch_config", "asp_batch_get_config",
+           "asp_batch_run", "asp_batch_autotune"]
 
 MLP_PARAMS = 329220
 MLP_IN = 1024
@@ -73,6 +75,11 @@ class FitReport(ctypes.Structure):
                 ("theta", ctypes.c_double * (4 * MAX_ACTIVE)),
                 ("fit_px", ctypes.c_int64), ("init_source", ctypes.c_int32),
                 ("start_from_proposal", ctypes.c_int32), ("init", ctypes.c_double * 4)]
+
+
+class BatchReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("fields_stopped", ctypes.c_int64),
+                ("fields_failed", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
 class RunReport(ctypes.Structure):
@@ -134,10 +141,21 @@ def lib():
         L.asp_mlp_forward.argtypes = [vp, vp, i64, vp]
         L.asp_mlp_weights.argtypes = [vp, vp]
         L.asp_residual_sumsq.argtypes = [vp, P(f64)]
+        i32 = ctypes.c_int32
+        L.asp_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, P(Options), P(vp)]
+        L.asp_batch_destroy.argtypes = [vp]
+        L.asp_batch_destroy.restype = None
+        L.asp_batch_last_error.argtypes = [vp]
+        L.asp_batch_last_error.restype = ctypes.c_char_p
+        L.asp_batch_field.argtypes = [vp, i32, P(vp)]
+        L.asp_batch_config.argtypes = [vp, i32, i32, i32]
+        L.asp_batch_get_config.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
+        L.asp_batch_run.argtypes = [vp, i64, P(BatchReport)]
+        L.asp_batch_autotune.argtypes = [vp, i64, P(i32), P(i32), P(i32)]
         L.asp_fit_profile.argtypes = [vp, vp, ctypes.c_int32]
         for name in EXPORTS:
             if name not in ("asp_destroy", "asp_last_error", "asp_mlp_destroy",
-                            "asp_mlp_last_error"):
+                            "asp_mlp_last_error", "asp_batch_destroy", "asp_batch_last_error"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -333,6 +351,87 @@ class Context:
         a, w = ctypes.c_double(), ctypes.c_double()
         self._check(lib().asp_psf_gauss(self._ctx, ctypes.byref(a), ctypes.byref(w)))
         return a.value, w.value
+
+
+class Batch:
+    """Many independent fields deconvolved by one persistent, graph-captured
+    launch.  fields: a list of (dirty, psf, gain, threshold) with host float32
+    images.  field(i) returns a Context view of field i."""
+
+    def __init__(self, fields, **options):
+        n = len(fields)
+        opt = default_options(**options)
+        self._keep = []
+        dptr = (ctypes.c_void_p * n)()
+        pptr = (ctypes.c_void_p * n)()
+        H = (ctypes.c_int64 * n)()
+        W = (ctypes.c_int64 * n)()
+        Hp = (ctypes.c_int64 * n)()
+        Wp = (ctypes.c_int64 * n)()
+        gain = (ctypes.c_float * n)()
+        thr = (ctypes.c_float * n)()
+        for i, (dirty, psf, g, t) in enumerate(fields):
+            d = np.ascontiguousarray(dirty, dtype=np.float32)
+            q = np.ascontiguousarray(psf, dtype=np.float32)
+            self._keep += [d, q]
+            dptr[i], pptr[i] = d.ctypes.data, q.ctypes.data
+            H[i], W[i] = d.shape
+            Hp[i], Wp[i] = q.shape
+            gain[i], thr[i] = float(g), float(t)
+        self._b = ctypes.c_void_p()
+        rc = lib().asp_batch_create(n, dptr, H, W, pptr, Hp, Wp, gain, thr, ctypes.byref(opt),
+                                    ctypes.byref(self._b))
+        if rc != ASP_OK:
+            raise AspError(rc, "asp_batch_create failed")
+        self._keep = None
+        self.n = n
+        self.shapes = [(int(H[i]), int(W[i])) for i in range(n)]
+
+    def close(self):
+        if self._b:
+            lib().asp_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc < 0:
+            raise AspError(rc, lib().asp_batch_last_error(self._b).decode())
+        return rc
+
+    def field(self, i: int) -> "Context":
+        c = ctypes.c_void_p()
+        self._check(lib().asp_batch_field(self._b, int(i), ctypes.byref(c)))
+        ctx = Context.__new__(Context)
+        ctx._ctx = c
+        ctx.H, ctx.W = self.shapes[i]
+        ctx._owner = self
+        ctx.close = lambda: None            # the batch owns it
+        return ctx
+
+    def config(self, team_size=0, solo_tiles=0, min_tiles=0):
+        self._check(lib().asp_batch_config(self._b, int(team_size), int(solo_tiles),
+                                           int(min_tiles)))
+
+    def get_config(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(4)]
+        self._check(lib().asp_batch_get_config(self._b, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("team_size", "solo_tiles", "min_tiles", "grid"), [x.value for x in v]))
+
+    def run(self, n_iter: int) -> dict:
+        r = BatchReport()
+        self._check(lib().asp_batch_run(self._b, int(n_iter), ctypes.byref(r)))
+        return {f: getattr(r, f) for f, _ in BatchReport._fields_}
+
+    def autotune(self, probe_iter: int = 10) -> dict:
+        v = [ctypes.c_int32() for _ in range(3)]
+        self._check(lib().asp_batch_autotune(self._b, int(probe_iter),
+                                             *[ctypes.byref(x) for x in v]))
+        return dict(zip(("team_size", "solo_tiles", "min_tiles"), [x.value for x in v]))
 
 
 class Mlp:

@@ -76,7 +76,8 @@ constexpr int kPartStride = kNOutMax + 3;                      // + F, chi2 (FP6
 constexpr int kMaxGroups = 64;     // partial rows beyond the grid, one per arrival group
 
 struct FitGlobal {
-    int32_t m, n, done, pad0;
+    int32_t m, n, done, cmd;            // cmd, field: the batched kernel's command
+    int32_t field, pad0;
     double th_e[kMaxN];                 // parameters under evaluation
     double th_old[kMaxN];               // stored parameters of the old members
     unsigned int gen;                   // publication counter
@@ -170,5 +171,20 @@ hipError_t launch_sumsq(const float *img, int64_t n, double *part, int nblk, dou
                         hipStream_t s);
 hipError_t fit_kernel_setup();
 int fit_grid_size(int device);
+
+// The batched kernel: many fields, one persistent launch (fit.hip).
+struct BatchArgs {
+    const Params *fields;          // n_fields parameter blocks (device)
+    const int32_t *order;          // fields in the order teams take them
+    unsigned int *queue;           // next position in order (reset before each launch)
+    FitGlobal *fg;                 // one per team
+    double *partials;              // per team (T + groups) x kPartStride
+    int64_t n_iter;                // iterations per field in this launch
+    int64_t solo_peak_px;          // peak search by the leader alone up to this many pixels
+    int64_t solo_update_px;        // update by the leader alone up to this bounding box
+    int32_t n_fields, team_size, solo_tiles, min_tiles;
+};
+int batch_grid_size(int device);
+hipError_t launch_batch(const BatchArgs &b, int grid, hipStream_t s);
 
 }  // namespace asp

@@ -26,6 +26,7 @@
 #include <math.h>
 
 #include "asp_device.h"
+#include "cycle.h"
 
 namespace asp {
 
@@ -72,6 +73,9 @@ struct WGShared {
     int32_t alt_pending, chose_prop;
     double sel[2];                 // peak pixel (x, y): the active set is selected around it
     int32_t nch, sel_done;
+    // batched fields (leader and followers)
+    int32_t cmd, fld, go;
+    int64_t k_target, upx;
     // control
     unsigned long long tmark;      // phase timer mark (thread 0)
     unsigned int gen;
@@ -1065,6 +1069,123 @@ __device__ __forceinline__ void arrive(const Params &p, FitGlobal *G, WGShared &
     if (t == 0) __hip_atomic_fetch_add(&G->top, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The peak and the stop test (Sect. 2 steps 1 and 4) of one fit, thread 0 of
+// the leading work-group: sets S.idx, S.peak, S.stop and the fit's
+// bookkeeping.  `abort` reports a wait that ran out before it.
+__device__ __forceinline__ void fit_begin(const Params &p, WGShared &S, bool abort)
+{
+    DevState *st = p.st;
+    atomicAdd(&st->prof[kPFits], 1ull);
+    st->fit_ready = 0;
+    const unsigned long long key = st->peak_key;
+    st->peak_key = 0ull;
+    int64_t idx = st->forced_idx >= 0
+                      ? st->forced_idx
+                      : (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+    const bool bad_idx = (st->forced_idx < 0 && key == 0ull) || idx < 0 || idx >= p.H * p.W;
+    st->forced_idx = -1;
+    S.stop = 0;
+    if (abort) S.stop = ASP_ERR_DEVICE;
+    else if (bad_idx) S.stop = ASP_ERR_STATE;
+    if (bad_idx) idx = 0;
+    const float v = p.R[idx];
+    if (S.stop == 0) {
+        if (fabs((double)v) < p.threshold) S.stop = ASP_STOP_THRESHOLD;
+        else if (st->k >= p.max_iter) S.stop = ASP_STOP_MAXITER;
+        else if (st->L >= p.cap) S.stop = ASP_ERR_CAPACITY;
+    }
+    st->idx = idx;
+    st->peak = v;
+    S.idx = idx;
+    S.peak = (double)v;
+    S.pass = 0;
+    S.trials_total = 0;
+    S.used_fallback = 0;
+    S.use_prop = (p.use_proposal && st->have_proposal) ? 1 : 0;
+    if (S.stop) st->stop = S.stop;
+}
+
+// Start values, active set, the LM trials and the commit of one fit, by the
+// leading work-group (share 0 of nwg).  A trial larger than p.solo_tiles tiles
+// is published (with G->cmd = cmd when cmd != 0) and shared by the nwg
+// work-groups.  Returns false when a wait ran out; the context is then marked
+// with ASP_ERR_DEVICE.
+__device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShared &S, float *tile,
+                                           double *red, double *A, double *He, double *Hc,
+                                           int nwg, int cmd)
+{
+    DevState *st = p.st;
+    const int t = threadIdx.x;
+    const int ngroups = (nwg + kGroup - 1) / kGroup;
+    mark(S);
+    setup_fit(p, G, S, S.use_prop != 0);
+    lap(p, S, kPSetup);
+    for (;;) {
+        // the trial at S.th_e
+        prepare(p, S, S.m, S.th_e, S.th_old);
+        const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
+        lap(p, S, kPPrepare);
+        if (ntiles <= p.solo_tiles) {
+            // small: the leading work-group alone, no publication
+            evaluate_row(p, S, tile, red, 0, 1, p.partials);
+            lap(p, S, kPEval);
+            reduce_partials(p, S, 0, 1, He);
+            lap(p, S, kPReduce);
+        } else {
+            // large: every work-group takes a share
+            const int geff = eval_groups(ntiles, nwg, p.min_tiles);
+            const int ng_eval = (geff + kGroup - 1) / kGroup;
+            if (t < S.n) G->th_e[t] = S.th_e[t];
+            if (t == 0 && cmd) G->cmd = cmd;
+            publish(G);
+            evaluate_row(p, S, tile, red, 0, geff, p.partials);
+            lap(p, S, kPEval);
+            arrive(p, G, S, 0, nwg, geff);
+            lap(p, S, kPArrive);
+            if (t == 0) {
+                S.abort = spin_until(&G->top, (unsigned)ngroups) ? 0 : 1;
+                __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            lap(p, S, kPWait);
+            __syncthreads();
+            if (S.abort) {
+                if (t == 0) st->stop = ASP_ERR_DEVICE;
+                __syncthreads();
+                return false;
+            }
+            if (ng_eval > 1) reduce_partials(p, S, nwg, nwg + ng_eval, He);
+            else reduce_partials(p, S, 0, geff, He);
+            lap(p, S, kPReduce);
+        }
+        lm_step(p, S, He, Hc, A);
+        lap(p, S, kPLmStep);
+        if (t == 0) {
+            const unsigned long long npx = (unsigned long long)S.npx_e;
+            st->sum_eval_px += npx;
+            st->sum_gram_flops += npx * (unsigned long long)((S.n + 1) * (S.n + 2));
+            atomicAdd(&st->prof[kPTrials], 1ull);
+            atomicAdd(&st->prof[kPEvalPx], npx);
+        }
+        if (!S.finished) continue;
+        if (S.use_prop && S.chose_prop && !S.converged && S.pass == 0) {
+            // LM started from the proposal and did not converge: the simple
+            // values instead
+            if (t == 0) {
+                S.trials_total += S.trials;
+                S.used_fallback = 1;
+                S.pass = 1;
+            }
+            __syncthreads();
+            setup_fit(p, G, S, false);
+            continue;
+        }
+        mark(S);
+        commit(p, S);
+        lap(p, S, kPCommit);
+        return true;
+    }
+}
+
 __global__ __launch_bounds__(kT) void k_fit(Params p)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -1078,7 +1199,6 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
     DevState *st = p.st;
     const int t = threadIdx.x;
     const int wg = blockIdx.x, nwg = gridDim.x;
-    const int ngroups = (nwg + kGroup - 1) / kGroup;
 
     // Nothing writes the stop flag before every work-group has checked in, so
     // all of them agree here.
@@ -1118,116 +1238,216 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
         S.abort = spin_until(&G->top, (unsigned)nwg) ? 0 : 1;
         __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         lap(p, S, kPCheckin);
-        atomicAdd(&st->prof[kPFits], 1ull);
-        // the peak and the stop test (Sect. 2 steps 1 and 4)
-        st->fit_ready = 0;
-        const unsigned long long key = st->peak_key;
-        st->peak_key = 0ull;
-        int64_t idx = st->forced_idx >= 0
-                          ? st->forced_idx
-                          : (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
-        const bool bad_idx = (st->forced_idx < 0 && key == 0ull) || idx < 0 || idx >= p.H * p.W;
-        st->forced_idx = -1;
-        S.stop = 0;
-        if (S.abort) S.stop = ASP_ERR_DEVICE;
-        else if (bad_idx) S.stop = ASP_ERR_STATE;
-        if (bad_idx) idx = 0;
-        const float v = p.R[idx];
-        if (S.stop == 0) {
-            if (fabs((double)v) < p.threshold) S.stop = ASP_STOP_THRESHOLD;
-            else if (st->k >= p.max_iter) S.stop = ASP_STOP_MAXITER;
-            else if (st->L >= p.cap) S.stop = ASP_ERR_CAPACITY;
-        }
-        st->idx = idx;
-        st->peak = v;
-        S.idx = idx;
-        S.peak = (double)v;
-        S.pass = 0;
-        S.trials_total = 0;
-        S.used_fallback = 0;
-        S.use_prop = (p.use_proposal && st->have_proposal) ? 1 : 0;
+        fit_begin(p, S, S.abort != 0);
         // workers read this only after a publication of this fit
         G->done = S.stop ? 1 : 0;
-        if (S.stop) st->stop = S.stop;
     }
     __syncthreads();
-    if (S.stop) {
-        publish(G);
-        return;
-    }
-    mark(S);
-    setup_fit(p, G, S, S.use_prop != 0);
-    lap(p, S, kPSetup);
-    for (;;) {
-        // the trial at S.th_e
-        prepare(p, S, S.m, S.th_e, S.th_old);
-        const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
-        lap(p, S, kPPrepare);
-        if (ntiles <= p.solo_tiles) {
-            // small: work-group 0 alone, no publication
-            evaluate_row(p, S, tile, red, 0, 1, p.partials);
-            lap(p, S, kPEval);
-            reduce_partials(p, S, 0, 1, He);
-            lap(p, S, kPReduce);
-        } else {
-            // large: every work-group takes a share
-            const int geff = eval_groups(ntiles, nwg, p.min_tiles);
-            const int ng_eval = (geff + kGroup - 1) / kGroup;
-            if (t < S.n) G->th_e[t] = S.th_e[t];
-            publish(G);
-            evaluate_row(p, S, tile, red, 0, geff, p.partials);
-            lap(p, S, kPEval);
-            arrive(p, G, S, 0, nwg, geff);
-            lap(p, S, kPArrive);
-            if (t == 0) {
-                S.abort = spin_until(&G->top, (unsigned)ngroups) ? 0 : 1;
-                __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            lap(p, S, kPWait);
-            __syncthreads();
-            if (S.abort) {
-                if (t == 0) { st->stop = ASP_ERR_DEVICE; G->done = 1; }
-                publish(G);
-                return;
-            }
-            if (ng_eval > 1) reduce_partials(p, S, nwg, nwg + ng_eval, He);
-            else reduce_partials(p, S, 0, geff, He);
-            lap(p, S, kPReduce);
-        }
-        lm_step(p, S, He, Hc, A);
-        lap(p, S, kPLmStep);
-        if (t == 0) {
-            const unsigned long long npx = (unsigned long long)S.npx_e;
-            st->sum_eval_px += npx;
-            st->sum_gram_flops += npx * (unsigned long long)((S.n + 1) * (S.n + 2));
-            atomicAdd(&st->prof[kPTrials], 1ull);
-            atomicAdd(&st->prof[kPEvalPx], npx);
-        }
-        if (!S.finished) continue;
-        if (S.use_prop && S.chose_prop && !S.converged && S.pass == 0) {
-            // the learned start did not converge: the simple values instead
-            if (t == 0) {
-                S.trials_total += S.trials;
-                S.used_fallback = 1;
-                S.pass = 1;
-            }
-            __syncthreads();
-            setup_fit(p, G, S, false);
-            continue;
-        }
-        mark(S);
-        commit(p, S);
-        lap(p, S, kPCommit);
+    if (!S.stop) {
+        fit_trials(p, G, S, tile, red, A, He, Hc, nwg, 0);
         if (t == 0) G->done = 1;
+    }
+    publish(G);
+}
+
+// ===========================================================================
+// Batched fields: one persistent launch for many independent fields.
+//
+// The work-groups form teams of T.  Work-groups are dealt to the 8 XCDs round
+// robin, so a team is made of work-groups with equal blockIdx % 8: one XCD,
+// one L2 for the team's field.  A team takes fields from a queue, largest
+// first, and runs each field's minor cycle for up to n_iter iterations:
+// rank 0 leads as work-group 0 of k_fit does and the others follow its
+// commands -- a share of the peak search, a share of an LM trial, a share of
+// the residual update, or exit.  Every command is acknowledged by every member
+// before the next one is published; every wait is bounded.
+// ===========================================================================
+
+enum { kCmdPeak = 1, kCmdEval = 2, kCmdUpdate = 3, kCmdExit = 4 };
+
+// The field's parameters with the team's exchange buffers and the batch's
+// tile thresholds (thread 0 writes, the work-group reads after the barrier).
+__device__ __forceinline__ void load_field(const BatchArgs &b, int f, FitGlobal *G, double *parts,
+                                           Params &P)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        P = b.fields[f];
+        P.fg = G;
+        P.partials = parts;
+        P.solo_tiles = b.team_size == 1 ? 0x7FFFFFFF : b.solo_tiles;
+        P.min_tiles = b.min_tiles;
+    }
+    __syncthreads();
+}
+
+// The leader's wait for the team's arrivals; false when it ran out.
+__device__ __forceinline__ bool team_wait(FitGlobal *G, WGShared &S, int ngroups)
+{
+    if (threadIdx.x == 0) {
+        S.abort = spin_until(&G->top, (unsigned)ngroups) ? 0 : 1;
+        __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return S.abort == 0;
+}
+
+__global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    float *tile = reinterpret_cast<float *>(lds);
+    double *A = reinterpret_cast<double *>(lds);
+    double *He = reinterpret_cast<double *>(lds + kTileBytes);
+    double *Hc = He + kMaxN * kMaxN;
+    __shared__ WGShared S;
+    __shared__ double red[kT];
+    __shared__ Params P;
+    __shared__ int32_t cur_field;
+    const int t = threadIdx.x;
+    const int T = b.team_size;
+    const int per_xcd = (int)gridDim.x / 8;
+    const int xcd = (int)blockIdx.x % 8, slot = (int)blockIdx.x / 8;
+    const int team = xcd * (per_xcd / T) + slot / T;
+    const int rank = slot % T;
+    const int ngroups = (T + kGroup - 1) / kGroup;
+    FitGlobal *G = b.fg + team;
+    double *parts = b.partials + (int64_t)team * (T + ngroups) * kPartStride;
+
+    // check in: every follower reads the generation before the leader publishes
+    if (t == 0) {
+        S.gen = __hip_atomic_load(&G->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        S.abort = 0;
+        cur_field = -1;
+        if (rank != 0)
+            __hip_atomic_fetch_add(&G->top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+
+    if (rank != 0) {
+        for (;;) {
+            if (!wait_publish(G, S)) return;      // the leader marks its field
+            if (t == 0) {
+                S.cmd = G->cmd;
+                S.fld = G->field;
+            }
+            __syncthreads();
+            const int cmd = S.cmd;
+            if (cmd == kCmdExit || S.fld < 0 || S.fld >= b.n_fields) return;
+            if (S.fld != cur_field) {
+                load_field(b, S.fld, G, parts, P);
+                if (t == 0) cur_field = S.fld;
+                __syncthreads();
+            }
+            int geff = 0;
+            if (cmd == kCmdPeak) {
+                peak_scan(P.R, P.H * P.W, (uint32_t)rank, (uint32_t)T, P.st);
+            } else if (cmd == kCmdUpdate) {
+                update_tiles(P, rank, T);
+            } else if (cmd == kCmdEval) {
+                prepare(P, S, G->m, G->th_e, G->th_old);
+                const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
+                geff = eval_groups(ntiles, T, P.min_tiles);
+                if (rank < geff)
+                    evaluate_row(P, S, tile, red, rank, geff,
+                                 P.partials + (int64_t)rank * kPartStride);
+            }
+            arrive(P, G, S, rank, T, geff);
+        }
+    }
+
+    // the leader
+    if (t == 0) {
+        if (T > 1) S.abort = spin_until(&G->top, (unsigned)(T - 1)) ? 0 : 1;
+        __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    bool ok = S.abort == 0;
+    while (ok) {
+        if (t == 0) {
+            const unsigned q = atomicAdd(b.queue, 1u);
+            S.fld = q < (unsigned)b.n_fields ? b.order[q] : -1;
+        }
+        __syncthreads();
+        if (S.fld < 0) break;
+        load_field(b, S.fld, G, parts, P);
+        if (t == 0) {
+            cur_field = S.fld;
+            G->field = S.fld;
+            S.k_target = P.st->k + b.n_iter;
+        }
+        for (;;) {
+            if (t == 0) S.go = (P.st->stop == 0 && P.st->k < S.k_target) ? 1 : 0;
+            __syncthreads();
+            if (!S.go) break;
+            // the peak of |R| (Sect. 2 step 1)
+            const int64_t npx = P.H * P.W;
+            if (T == 1 || npx <= b.solo_peak_px) {
+                peak_scan(P.R, npx, 0u, 1u, P.st);
+            } else {
+                if (t == 0) G->cmd = kCmdPeak;
+                publish(G);
+                peak_scan(P.R, npx, 0u, (uint32_t)T, P.st);
+                arrive(P, G, S, 0, T, 0);
+                if (!team_wait(G, S, ngroups)) { ok = false; break; }
+            }
+            __syncthreads();
+            // the stop test and the fit (Sect. 2 step 4; Sect. 3)
+            if (t == 0) fit_begin(P, S, false);
+            __syncthreads();
+            if (S.stop) break;
+            if (!fit_trials(P, G, S, tile, red, A, He, Hc, T, kCmdEval)) { ok = false; break; }
+            // the residual update (Sect. 2 step 3)
+            if (t == 0) {
+                const int32_t *bb = P.st->bb;
+                S.upx = (int64_t)(bb[1] - bb[0] + 1) * (int64_t)(bb[3] - bb[2] + 1);
+            }
+            __syncthreads();
+            if (T == 1 || S.upx <= b.solo_update_px) {
+                update_tiles(P, 0, 1);
+            } else {
+                if (t == 0) G->cmd = kCmdUpdate;
+                publish(G);
+                update_tiles(P, 0, T);
+                arrive(P, G, S, 0, T, 0);
+                if (!team_wait(G, S, ngroups)) { ok = false; break; }
+            }
+        }
+    }
+    if (!ok && t == 0 && cur_field >= 0) P.st->stop = ASP_ERR_DEVICE;
+    __syncthreads();
+    if (T > 1) {
+        if (t == 0) G->cmd = kCmdExit;
         publish(G);
-        return;
     }
 }
 
+__global__ void k_batch_reset(unsigned int *queue) { *queue = 0u; }
+
 hipError_t fit_kernel_setup()
 {
-    return hipFuncSetAttribute((const void *)k_fit, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void *)k_fit,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFitLds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)kFitLds);
+}
+
+int batch_grid_size(int device)
+{
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch, kT,
+                                                     kFitLds) != hipSuccess || per_cu < 1)
+        return 0;
+    return (cus * per_cu / 8) * 8;      // whole XCD rows
+}
+
+hipError_t launch_batch(const BatchArgs &b, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, b.queue);
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kT), kFitLds, s, b);
+    return hipGetLastError();
 }
 
 int fit_grid_size(int device)

@@ -7,76 +7,15 @@
 #include <math.h>
 
 #include "asp_device.h"
+#include "cycle.h"
 
 namespace asp {
-
-// ===========================================================================
-// Peak search: the largest |R|, the lowest row-major index winning ties.
-// Each thread walks its elements in increasing index order keeping the first
-// strict maximum; the block combines packed keys (|v| bits << 32 | ~idx), whose
-// integer maximum is exactly that rule, and one 64-bit atomicMax per block
-// makes the result independent of block order.
-// ===========================================================================
-
-__device__ inline void peak_take(float v, uint32_t i, float &bv, uint32_t &bi)
-{
-    float a = fabsf(v);
-    if (a > bv) { bv = a; bi = i; }
-}
-
-__device__ inline void peak_take4(const float4 &v, uint32_t i4, float &bv, uint32_t &bi)
-{
-    peak_take(v.x, 4 * i4 + 0, bv, bi);
-    peak_take(v.y, 4 * i4 + 1, bv, bi);
-    peak_take(v.z, 4 * i4 + 2, bv, bi);
-    peak_take(v.w, 4 * i4 + 3, bv, bi);
-}
-
-__device__ inline unsigned long long wave_max_u64(unsigned long long v)
-{
-    for (int off = 32; off > 0; off >>= 1) {
-        unsigned long long o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
 
 __global__ __launch_bounds__(256) void k_peak(const float *__restrict__ R, int64_t n,
                                               DevState *st)
 {
     if (st->stop) return;
-    const uint32_t n4 = (uint32_t)(n >> 2);
-    const float4 *R4 = reinterpret_cast<const float4 *>(R);
-    const uint32_t stride = gridDim.x * blockDim.x;
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    float bv = -1.0f;
-    uint32_t bi = 0;
-    for (; i + 3 * stride < n4; i += 4 * stride) {
-        float4 v0 = R4[i], v1 = R4[i + stride], v2 = R4[i + 2 * stride], v3 = R4[i + 3 * stride];
-        peak_take4(v0, i, bv, bi);
-        peak_take4(v1, i + stride, bv, bi);
-        peak_take4(v2, i + 2 * stride, bv, bi);
-        peak_take4(v3, i + 3 * stride, bv, bi);
-    }
-    for (; i < n4; i += stride) peak_take4(R4[i], i, bv, bi);
-    uint32_t tail = (uint32_t)(n - 4 * (int64_t)n4);
-    if (blockIdx.x == 0 && threadIdx.x < tail) {
-        uint32_t j = 4 * n4 + threadIdx.x;
-        peak_take(R[j], j, bv, bi);
-    }
-    unsigned long long key = 0;
-    if (bv >= 0.0f)
-        key = ((unsigned long long)__float_as_uint(bv) << 32) | (unsigned long long)(0xFFFFFFFFu - bi);
-    key = wave_max_u64(key);
-    __shared__ unsigned long long wk[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) wk[wave] = key;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long k = wk[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) k = wk[w] > k ? wk[w] : k;
-        atomicMax(&st->peak_key, k);
-    }
+    peak_scan(R, n, blockIdx.x, gridDim.x, st);
 }
 
 hipError_t launch_peak(const Params &p, int grid, hipStream_t s)
@@ -107,79 +46,10 @@ hipError_t launch_peak_decode(const Params &p, hipStream_t s)
     return hipGetLastError();
 }
 
-// ===========================================================================
-// Residual update: R += sum over the plan's rects of sign * G on the rect,
-// each pixel read and written once (Sect. 2 step 3 with the Gaussian beam).
-// Blocks stride over 64 x 4 tiles of the plan's bounding box and skip tiles
-// that meet no rect.
-// ===========================================================================
-
 __global__ __launch_bounds__(256) void k_update(Params p)
 {
-    DevState *st = p.st;
-    if (!st->fit_ready) return;
-    __shared__ int32_t rb[kMaxRects][4];
-    __shared__ int32_t rcx[kMaxRects], rcy[kMaxRects];
-    __shared__ float rfx[kMaxRects], rfy[kMaxRects], ramp[kMaxRects], rinv[kMaxRects];
-    __shared__ int32_t nr_s, bb_s[4];
-    __shared__ unsigned long long cnt_s[4];
-    const int t = threadIdx.x;
-    if (t == 0) {
-        nr_s = st->n_rects;
-        for (int i = 0; i < 4; ++i) bb_s[i] = st->bb[i];
-    }
-    if (t < st->n_rects) {
-        const Rect &R = st->rects[t];
-        rb[t][0] = R.r0; rb[t][1] = R.r1; rb[t][2] = R.c0; rb[t][3] = R.c1;
-        double cx = floor(R.x + 0.5), cy = floor(R.y + 0.5);
-        rcx[t] = (int32_t)cx;
-        rcy[t] = (int32_t)cy;
-        rfx[t] = (float)(R.x - cx);
-        rfy[t] = (float)(R.y - cy);
-        ramp[t] = (float)((double)R.sign * R.a);
-        rinv[t] = (float)(1.0 / (2.0 * R.s * R.s));
-    }
-    __syncthreads();
-    const int nr = nr_s;
-    const int32_t br0 = bb_s[0], br1 = bb_s[1], bc0 = bb_s[2], bc1 = bb_s[3];
-    const int ntx = (bc1 - bc0 + 64) / 64, nty = (br1 - br0 + 4) / 4;
-    const int64_t ntiles = (int64_t)ntx * nty;
-    unsigned long long cnt = 0;
-    const int lr = t >> 6, lc = t & 63;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int32_t tr0 = br0 + (int32_t)(tile / ntx) * 4;
-        const int32_t tc0 = bc0 + (int32_t)(tile % ntx) * 64;
-        bool any = false;
-        for (int i = 0; i < nr; ++i)
-            any |= (rb[i][0] <= tr0 + 3 && tr0 <= rb[i][1] && rb[i][2] <= tc0 + 63 && tc0 <= rb[i][3]);
-        if (!any) continue;
-        const int32_t r = tr0 + lr, c = tc0 + lc;
-        if (r > br1 || c > bc1) continue;
-        float acc = 0.0f;
-        bool hit = false;
-        for (int i = 0; i < nr; ++i) {
-            if (r < rb[i][0] || r > rb[i][1] || c < rb[i][2] || c > rb[i][3]) continue;
-            float dx = (float)(c - rcx[i]) - rfx[i];
-            float dy = (float)(r - rcy[i]) - rfy[i];
-            acc += ramp[i] * __expf(-(dx * dx + dy * dy) * rinv[i]);
-            hit = true;
-        }
-        if (hit) {
-            float *px = p.R + (int64_t)r * p.W + c;
-            *px = *px + acc;
-            ++cnt;
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-    if ((t & 63) == 0) cnt_s[t >> 6] = cnt;
-    __syncthreads();
-    if (t == 0) {
-        unsigned long long c = cnt_s[0] + cnt_s[1] + cnt_s[2] + cnt_s[3];
-        if (c) {
-            atomicAdd(&st->update_px, c);
-            atomicAdd(&st->sum_update_px, c);
-        }
-    }
+    if (!p.st->fit_ready) return;
+    update_tiles(p, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_update(const Params &p, int grid, hipStream_t s)

@@ -659,3 +659,293 @@ asp_status asp_counts(asp_ctx *c, int64_t *k, int64_t *L)
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Batched fields: a set of contexts run by one persistent launch (k_batch),
+// captured once in a HIP graph per configuration and replayed.
+// ===========================================================================
+
+struct asp_batch {
+    std::vector<asp_ctx *> ctx;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    asp::Params *d_params = nullptr;
+    int32_t *d_order = nullptr;
+    unsigned int *d_queue = nullptr;
+    asp::FitGlobal *d_fg = nullptr;
+    double *d_partials = nullptr;
+    int grid = 0;
+    int team = 8, solo_tiles = 8, min_tiles = 2;
+    int64_t solo_peak_px = 65536, solo_update_px = 16384;
+    // the captured graph and the configuration it was captured with
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t g_niter = -1;
+    int g_team = 0, g_solo = 0, g_min = 0;
+    std::string err;
+};
+
+namespace {
+
+asp_status bfail(asp_batch *b, asp_status s, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return s;
+}
+
+#define BATCH_HIP(b, call)                                                            \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return bfail((b), ASP_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+void batch_release(asp_batch *b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (asp_ctx *c : b->ctx) asp_destroy(c);
+    (void)hipFree(b->d_params); (void)hipFree(b->d_order); (void)hipFree(b->d_queue);
+    (void)hipFree(b->d_fg); (void)hipFree(b->d_partials);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+bool team_ok(const asp_batch *b, int team)
+{
+    const int per_xcd = b->grid / 8;
+    return team >= 1 && team <= 32 && per_xcd % team == 0;
+}
+
+// Capture the reset and the persistent launch for the current configuration.
+asp_status batch_capture(asp_batch *b, int64_t n_iter)
+{
+    if (b->exec && b->g_niter == n_iter && b->g_team == b->team && b->g_solo == b->solo_tiles &&
+        b->g_min == b->min_tiles)
+        return ASP_OK;
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    asp::BatchArgs a{};
+    a.fields = b->d_params;
+    a.order = b->d_order;
+    a.queue = b->d_queue;
+    a.fg = b->d_fg;
+    a.partials = b->d_partials;
+    a.n_iter = n_iter;
+    a.solo_peak_px = b->solo_peak_px;
+    a.solo_update_px = b->solo_update_px;
+    a.n_fields = (int32_t)b->ctx.size();
+    a.team_size = b->team;
+    a.solo_tiles = b->solo_tiles;
+    a.min_tiles = b->min_tiles;
+    BATCH_HIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = asp::launch_batch(a, b->grid, b->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return bfail(b, ASP_ERR_DEVICE, std::string("capture of the batched launch: ") +
+                                            hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    BATCH_HIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->g_niter = n_iter;
+    b->g_team = b->team;
+    b->g_solo = b->solo_tiles;
+    b->g_min = b->min_tiles;
+    return ASP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+asp_status asp_batch_create(int32_t n_fields, const float *const *dirty, const int64_t *H,
+                            const int64_t *W, const float *const *psf, const int64_t *Hp,
+                            const int64_t *Wp, const float *gain, const float *threshold,
+                            const asp_options *opt, asp_batch **out)
+{
+    if (!out) return ASP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n_fields < 1 || !dirty || !H || !W || !psf || !Hp || !Wp || !gain || !threshold)
+        return ASP_ERR_INVALID_ARG;
+    if (opt && opt->stream) return ASP_ERR_INVALID_ARG;     // the batch owns its stream
+    asp_batch *b = new (std::nothrow) asp_batch;
+    if (!b) return ASP_ERR_NOMEM;
+    auto bail = [&](asp_status s) { batch_release(b); delete b; return s; };
+    if (hipGetDevice(&b->device) != hipSuccess) return bail(ASP_ERR_DEVICE);
+    if (hipStreamCreate(&b->stream) != hipSuccess) return bail(ASP_ERR_DEVICE);
+    asp_options o;
+    asp_default_options(&o);
+    if (opt) {
+        if (opt->struct_size != (int32_t)sizeof(asp_options)) return bail(ASP_ERR_INVALID_ARG);
+        o = *opt;
+    }
+    o.stream = b->stream;
+    for (int32_t i = 0; i < n_fields; ++i) {
+        asp_ctx *c = nullptr;
+        asp_status s = asp_create(dirty[i], H[i], W[i], psf[i], Hp[i], Wp[i], gain[i],
+                                  threshold[i], &o, &c);
+        if (s != ASP_OK) return bail(s);
+        b->ctx.push_back(c);
+    }
+    b->grid = asp::batch_grid_size(b->device);
+    if (b->grid < 8) return bail(ASP_ERR_DEVICE);
+    if (!team_ok(b, b->team)) b->team = b->grid / 8;
+    // the fields' parameter blocks and the order: largest first
+    std::vector<asp::Params> P(n_fields);
+    std::vector<int32_t> order(n_fields);
+    for (int32_t i = 0; i < n_fields; ++i) { P[i] = b->ctx[i]->P; order[i] = i; }
+    for (int32_t i = 1; i < n_fields; ++i)          // insertion sort, stable, by H*W descending
+        for (int32_t j = i; j > 0 && H[order[j]] * W[order[j]] > H[order[j - 1]] * W[order[j - 1]]; --j)
+            std::swap(order[j], order[j - 1]);
+    const size_t n_rows = (size_t)2 * b->grid;        // T + groups rows per team, T <= 32
+    if (dev_alloc(&b->d_params, (size_t)n_fields) != hipSuccess ||
+        dev_alloc(&b->d_order, (size_t)n_fields) != hipSuccess ||
+        dev_alloc(&b->d_queue, 1) != hipSuccess ||
+        dev_alloc(&b->d_fg, (size_t)b->grid) != hipSuccess ||
+        dev_alloc(&b->d_partials, n_rows * asp::kPartStride) != hipSuccess)
+        return bail(ASP_ERR_NOMEM);
+    if (hipMemcpy(b->d_params, P.data(), sizeof(asp::Params) * n_fields, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * n_fields, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(b->d_fg, 0, sizeof(asp::FitGlobal) * b->grid) != hipSuccess ||
+        hipMemset(b->d_queue, 0, sizeof(unsigned int)) != hipSuccess)
+        return bail(ASP_ERR_DEVICE);
+    *out = b;
+    return ASP_OK;
+}
+
+void asp_batch_destroy(asp_batch *b)
+{
+    batch_release(b);
+    delete b;
+}
+
+const char *asp_batch_last_error(const asp_batch *b)
+{
+    return b ? b->err.c_str() : "null batch";
+}
+
+asp_status asp_batch_field(asp_batch *b, int32_t i, asp_ctx **ctx)
+{
+    if (!b || !ctx || i < 0 || i >= (int32_t)b->ctx.size()) return ASP_ERR_INVALID_ARG;
+    *ctx = b->ctx[i];
+    return ASP_OK;
+}
+
+asp_status asp_batch_config(asp_batch *b, int32_t team_size, int32_t solo_tiles,
+                            int32_t min_tiles)
+{
+    if (!b) return ASP_ERR_INVALID_ARG;
+    if (team_size != 0 && !team_ok(b, team_size))
+        return bfail(b, ASP_ERR_INVALID_ARG, "team size must divide the work-groups of one XCD");
+    if (solo_tiles < -1 || min_tiles < 0) return ASP_ERR_INVALID_ARG;
+    if (team_size) b->team = team_size;
+    if (solo_tiles) b->solo_tiles = solo_tiles < 0 ? 0 : solo_tiles;
+    if (min_tiles) b->min_tiles = min_tiles;
+    return ASP_OK;
+}
+
+asp_status asp_batch_get_config(asp_batch *b, int32_t *team_size, int32_t *solo_tiles,
+                                int32_t *min_tiles, int32_t *grid)
+{
+    if (!b) return ASP_ERR_INVALID_ARG;
+    if (team_size) *team_size = b->team;
+    if (solo_tiles) *solo_tiles = b->solo_tiles;
+    if (min_tiles) *min_tiles = b->min_tiles;
+    if (grid) *grid = b->grid;
+    return ASP_OK;
+}
+
+asp_status asp_batch_run(asp_batch *b, int64_t n_iter, asp_batch_report *rep)
+{
+    if (!b || n_iter < 0) return ASP_ERR_INVALID_ARG;
+    for (asp_ctx *c : b->ctx)
+        if (c->phase != 0) return bfail(b, ASP_ERR_STATE, "a field is inside a step-API sequence");
+    int64_t k0 = 0;
+    for (asp_ctx *c : b->ctx) {
+        asp_status s = pull_all(c);
+        if (s != ASP_OK) return bfail(b, s, c->err);
+        k0 += c->st_host->k;
+    }
+    asp_status s = batch_capture(b, n_iter);
+    if (s != ASP_OK) return s;
+    hipEvent_t e0, e1;
+    BATCH_HIP(b, hipEventCreate(&e0));
+    BATCH_HIP(b, hipEventCreate(&e1));
+    hipError_t e = hipEventRecord(e0, b->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return bfail(b, ASP_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+    int64_t k1 = 0, stopped = 0, errors = 0;
+    for (asp_ctx *c : b->ctx) {
+        s = pull_all(c);
+        if (s != ASP_OK) return bfail(b, s, c->err);
+        k1 += c->st_host->k;
+        const int32_t st = c->st_host->stop;
+        stopped += st != 0;
+        errors += st < 0;
+    }
+    if (rep) {
+        rep->iterations = k1 - k0;
+        rep->fields_stopped = stopped;
+        rep->fields_failed = errors;
+        rep->ms = (double)ms;
+    }
+    return errors ? bfail(b, ASP_ERR_DEVICE, "a field failed (see its context)") : ASP_OK;
+}
+
+asp_status asp_batch_autotune(asp_batch *b, int64_t probe_iter, int32_t *team_size,
+                              int32_t *solo_tiles, int32_t *min_tiles)
+{
+    if (!b || probe_iter < 1) return ASP_ERR_INVALID_ARG;
+    // coordinate search on real chunks of the run: team size, then the solo
+    // threshold, then the least tiles per work-group; each probe is scored by
+    // iterations per second of its own chunk
+    auto score = [&](double *ips) -> asp_status {
+        asp_batch_report r{};
+        asp_status s = asp_batch_run(b, probe_iter, &r);
+        if (s != ASP_OK) return s;
+        *ips = r.ms > 0.0 ? 1e3 * (double)r.iterations / r.ms : 0.0;
+        return ASP_OK;
+    };
+    const int teams[] = {2, 4, 8, 16, 32};
+    const int solos[] = {4, 8, 16, 32};
+    const int mins[] = {1, 2, 4};
+    double best = -1.0;
+    int bt = b->team, bs = b->solo_tiles, bm = b->min_tiles;
+    for (int t : teams) {
+        if (!team_ok(b, t)) continue;
+        b->team = t; b->solo_tiles = bs; b->min_tiles = bm;
+        double v; asp_status s = score(&v);
+        if (s != ASP_OK) return s;
+        if (v > best) { best = v; bt = t; }
+    }
+    best = -1.0;
+    for (int so : solos) {
+        b->team = bt; b->solo_tiles = so; b->min_tiles = bm;
+        double v; asp_status s = score(&v);
+        if (s != ASP_OK) return s;
+        if (v > best) { best = v; bs = so; }
+    }
+    best = -1.0;
+    for (int mi : mins) {
+        b->team = bt; b->solo_tiles = bs; b->min_tiles = mi;
+        double v; asp_status s = score(&v);
+        if (s != ASP_OK) return s;
+        if (v > best) { best = v; bm = mi; }
+    }
+    b->team = bt; b->solo_tiles = bs; b->min_tiles = bm;
+    if (team_size) *team_size = bt;
+    if (solo_tiles) *solo_tiles = bs;
+    if (min_tiles) *min_tiles = bm;
+    return ASP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+"""Batched fields on the GPU: one persistent, graph-captured launch over
+fields of uneven size.  Each field is checked against the FP64 oracle in
+lockstep (one iteration per launch), and free runs over several graph replays
+against the invariants that hold at any size."""
+import numpy as np
+import pytest
+
+import oracle
+import skygen
+from parity import param_errors, RESID_TOL
+
+pytestmark = pytest.mark.gpu
+
+asp = pytest.importorskip("paper_1606_07872_amd")
+
+SIZES = [512, 96, 192, 64, 128]
+
+
+def small_fields(max_iter=400):
+    return [skygen.make_batch_field(n, 7000 + i, max_iter) for i, n in enumerate(SIZES)]
+
+
+def make_batch(fields, **kw):
+    return asp.Batch([(f.dirty, f.psf, f.gain, f.threshold) for f in fields],
+                     max_iter=fields[0].max_iter, max_active=5, **kw)
+
+
+@pytest.mark.parametrize("team", [4, 8])
+def test_batch_lockstep_per_field(team):
+    fields = small_fields()
+    b = make_batch(fields)
+    b.config(team_size=team)
+    print("batch config", b.get_config(), flush=True)
+    ctxs = [b.field(i) for i in range(len(fields))]
+    orcs = []
+    for f, c in zip(fields, ctxs):
+        ab, wb = c.psf_gauss()
+        orcs.append(oracle.Oracle(f.dirty, gain=f.gain, threshold=f.threshold,
+                                  max_iter=f.max_iter, max_active=5, alpha_b=ab, omega_b=wb,
+                                  cap=f.max_iter + 1))
+    n_strict = 0
+    for it in range(8):
+        pre = [(c.residual(), c.components_raw(), c.counts()[0]) for c in ctxs]
+        rep = b.run(1)
+        assert rep["fields_failed"] == 0
+        for i, (f, c, o) in enumerate(zip(fields, ctxs, orcs)):
+            R0, comps0, k0 = pre[i]
+            o.load_state(R0, comps0, k0)
+            orep = o.step()
+            k1, L1 = c.counts()
+            assert k1 == k0 + 1, (i, k0, k1)
+            comps1 = c.components_raw()
+            # the new component, before the loop gain, and the refitted members
+            new = comps1[-1].copy()
+            new[0] /= f.gain
+            assert np.all(param_errors(new[None, :], orep["theta"][:1]) <= 1.0) or \
+                not orep["converged"], (i, it, new, orep["theta"][0])
+            R1 = c.residual().astype(np.float64)
+            peak = float(np.abs(f.dirty).max())
+            assert np.abs(R1 - o.R).max() <= RESID_TOL * peak, (i, it)
+            n_strict += orep["converged"]
+    assert n_strict >= 30
+    b.close()
+
+
+def test_batch_replays_keep_invariants():
+    """Three replays of the captured launch (10 iterations per field each): every
+    field advances by 30 iterations and its residual equals the dirty image
+    minus its component list (evaluated by the oracle from scratch)."""
+    fields = small_fields()
+    b = make_batch(fields)
+    b.config(team_size=8)
+    for r in range(3):
+        rep = b.run(10)
+        assert rep["fields_failed"] == 0
+        print("replay", r, rep, flush=True)
+    for i, f in enumerate(fields):
+        c = b.field(i)
+        k, L = c.counts()
+        assert k == 30 and L == 30
+        ab, wb = c.psf_gauss()
+        o = oracle.Oracle(f.dirty, gain=f.gain, threshold=f.threshold, max_iter=f.max_iter,
+                          max_active=5, alpha_b=ab, omega_b=wb, cap=f.max_iter + 1)
+        o.load_state(f.dirty, c.components_raw(), k)
+        want = o.residual_from_scratch()
+        got = c.residual().astype(np.float64)
+        assert np.abs(got - want).max() <= RESID_TOL * float(np.abs(f.dirty).max()), i
+    b.close()
+
+
+def test_batch_autotune_picks_a_valid_config():
+    fields = small_fields()
+    b = make_batch(fields)
+    cfg = b.autotune(2)
+    print("autotuned", cfg, flush=True)
+    grid = b.get_config()["grid"]
+    assert (grid // 8) % cfg["team_size"] == 0
+    assert cfg["solo_tiles"] in (4, 8, 16, 32) and cfg["min_tiles"] in (1, 2, 4)
+    k = [b.field(i).counts()[0] for i in range(len(fields))]
+    assert all(v == k[0] for v in k) and k[0] > 0
+    b.close()
+
+
+def test_batch_rejects_bad_team_size():
+    fields = small_fields()[:2]
+    b = make_batch(fields)
+    with pytest.raises(asp.AspError):
+        b.config(team_size=3)
+    b.close()
