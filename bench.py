@@ -37,6 +37,7 @@ WORKLOADS = {
     "c4096": ("make_c4096", 4096),
     "c1024": ("make_c1024", 1000),
     "c128": ("make_c128", 0),
+    "batch": ("make_batch", 64),
 }
 
 PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
@@ -132,6 +133,73 @@ def learned_vs_plain(args, f, wpath, rep, secs, rms_plain, torch, asp):
     return out
 
 
+def bench_batch(args):
+    """64 independent fields of sizes in {256, 512, 1024, 2048}^2, each with its
+    own Gaussian PSF: aggregate iterations/s of one graph-captured persistent
+    launch (team size and tile thresholds from the autotuner) against the
+    same fields run one after another through asp_run, both from iteration 0."""
+    import torch
+
+    import paper_1606_07872_amd as asp
+    import skygen
+    t0 = time.time()
+    fields = skygen.make_batch(64, 64)
+    log(f"generated {len(fields)} fields, {sum(f.dirty.size for f in fields) / 1e6:.1f} Mpx, "
+        f"in {time.time() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    spec = [(f.dirty, f.psf, f.gain, f.threshold) for f in fields]
+    n_iter = args.steps
+    # the autotuner works on a batch of its own (its probes advance the fields)
+    b = asp.Batch(spec, max_iter=5000, max_active=5)
+    t1 = time.perf_counter()
+    cfg = b.autotune(args.probe)
+    log(f"autotuned {cfg} in {time.perf_counter() - t1:.1f}s")
+    b.close()
+    b = asp.Batch(spec, max_iter=5000, max_active=5)
+    b.config(**cfg)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rep = b.run(n_iter)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t1
+    value = rep["iterations"] / secs
+    log(f"batched: {rep} in {secs:.3f}s -> {value:.0f} iterations/s")
+    b.close()
+    seq_secs, seq_iter = 0.0, 0
+    for f in fields:
+        ctx = asp.Context(f.dirty, f.psf, f.gain, f.threshold, max_iter=5000, max_active=5)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc, r = ctx.run(n_iter)
+        torch.cuda.synchronize()
+        seq_secs += time.perf_counter() - t1
+        seq_iter += r["iterations"]
+        ctx.close()
+    seq = seq_iter / seq_secs
+    log(f"sequential: {seq_iter} iterations in {seq_secs:.3f}s -> {seq:.0f} iterations/s")
+    line = {
+        "metric": "aggregate minor-cycle iterations/s, batched fields",
+        "value": value,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": rep["iterations"],
+        "warmup": 0,
+        "ms_per_step": 1e3 * secs / max(rep["iterations"], 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"64 fields of 256^2..2048^2 ({sum(f.dirty.size for f in fields)} px), "
+                               f"Gaussian PSFs FWHM U[2.5, 6], {n_iter} iterations per field from 0, "
+                               "one graph-captured persistent launch", "seed": 64,
+                   "autotuned": cfg, "device_ms": rep["ms"]},
+        "sequential": {"value": seq, "iterations": seq_iter, "seconds": seq_secs,
+                       "speedup": value / seq if seq > 0 else None},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +217,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-versus-plain start comparison")
     ap.add_argument("--weights", default=None, help="proposal network weights (.npy)")
+    ap.add_argument("--probe", type=int, default=5,
+                    help="iterations per field of each autotuner probe (batch workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the minor cycle "
@@ -157,6 +227,9 @@ def main():
 
     import torch
 
+    if args.workload == "batch":
+        bench_batch(args)
+        return
     if args.calibrate_copy:
         n = 64 << 20                        # floats: 256 MiB read and 256 MiB written
         src = torch.ones(n, dtype=torch.float32, device="cuda")
