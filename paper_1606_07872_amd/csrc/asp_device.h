@@ -26,9 +26,13 @@ struct Rect {
 
 constexpr int kProfSlots = 12;
 
+constexpr int kPeakSlots = 64;   // wave-size: one slot per lane of the collecting wave
+
 // Mutable per-context state in device memory.
 struct DevState {
-    unsigned long long peak_key;   // packed (|v| bits << 32) | (0xFFFFFFFF - idx)
+    // packed keys (|v| bits << 32) | (0xFFFFFFFF - idx), one slot per
+    // work-group index mod kPeakSlots; the peak is their maximum
+    unsigned long long peak_keys[kPeakSlots];
     int32_t stop;                  // 0 running, ASP_STOP_*, or ASP_ERR_CAPACITY
     int32_t fit_ready;             // 1 between a fit and its residual update
     int64_t k;                     // iterations done
@@ -155,6 +159,31 @@ __device__ inline double width_cap(const Params &p)
     double m = p.max_width > 0.0 ? p.max_width
                                  : (double)(p.H < p.W ? p.H : p.W) / 8.0;
     return m > p.st->omega_b ? m : p.st->omega_b;
+}
+
+// The peak key: the maximum over the slots, read by the 64 lanes of wave 0
+// (lanes of other waves get 0).  With reset, the slots are cleared after the
+// read.  Every thread of the work-group must call it.
+__device__ inline unsigned long long collect_peak_key(DevState *st, bool reset,
+                                                      unsigned long long *lds_key)
+{
+    const int t = threadIdx.x;
+    if (t < 64) {
+        // atomic accesses: the slots are written by atomics at L2, possibly by
+        // this work-group moments before
+        unsigned long long k = __hip_atomic_load(&st->peak_keys[t], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+        if (reset)
+            __hip_atomic_store(&st->peak_keys[t], 0ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(k, off, 64);
+            k = o > k ? o : k;
+        }
+        if (t == 0) *lds_key = k;
+    }
+    __syncthreads();
+    return *lds_key;
 }
 
 // Launchers (kernels.hip).

@@ -73,7 +73,7 @@ __device__ inline void peak_scan(const float *__restrict__ R, int64_t n, uint32_
     if (threadIdx.x == 0) {
         unsigned long long k = wk[0];
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) k = wk[w] > k ? wk[w] : k;
-        atomicMax(&st->peak_key, k);
+        atomicMax(&st->peak_keys[rank % kPeakSlots], k);
     }
 }
 

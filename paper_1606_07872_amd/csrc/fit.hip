@@ -73,6 +73,7 @@ struct WGShared {
     int32_t alt_pending, chose_prop;
     double sel[2];                 // peak pixel (x, y): the active set is selected around it
     int32_t nch, sel_done;
+    unsigned long long key;        // the peak key of this fit (collect_peak_key)
     // batched fields (leader and followers)
     int32_t cmd, fld, go;
     int64_t k_target, upx;
@@ -1077,8 +1078,7 @@ __device__ __forceinline__ void fit_begin(const Params &p, WGShared &S, bool abo
     DevState *st = p.st;
     atomicAdd(&st->prof[kPFits], 1ull);
     st->fit_ready = 0;
-    const unsigned long long key = st->peak_key;
-    st->peak_key = 0ull;
+    const unsigned long long key = S.key;
     int64_t idx = st->forced_idx >= 0
                       ? st->forced_idx
                       : (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
@@ -1238,6 +1238,10 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
         S.abort = spin_until(&G->top, (unsigned)nwg) ? 0 : 1;
         __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         lap(p, S, kPCheckin);
+    }
+    __syncthreads();
+    collect_peak_key(st, true, &S.key);
+    if (t == 0) {
         fit_begin(p, S, S.abort != 0);
         // workers read this only after a publication of this fit
         G->done = S.stop ? 1 : 0;
@@ -1392,6 +1396,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
             }
             __syncthreads();
             // the stop test and the fit (Sect. 2 step 4; Sect. 3)
+            collect_peak_key(P.st, true, &S.key);
             if (t == 0) fit_begin(P, S, false);
             __syncthreads();
             if (S.stop) break;

@@ -28,9 +28,11 @@ hipError_t launch_peak(const Params &p, int grid, hipStream_t s)
 // does this inside the fit kernel).
 __global__ void k_peak_decode(Params p)
 {
+    __shared__ unsigned long long key_s;
     DevState *st = p.st;
     if (st->stop) return;
-    unsigned long long key = st->peak_key;
+    const unsigned long long key = collect_peak_key(st, false, &key_s);
+    if (threadIdx.x != 0) return;
     int64_t idx = (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
     if (key == 0ull || idx >= p.H * p.W) { st->stop = ASP_ERR_STATE; return; }
     float v = p.R[idx];
@@ -42,7 +44,7 @@ __global__ void k_peak_decode(Params p)
 
 hipError_t launch_peak_decode(const Params &p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_peak_decode, dim3(1), dim3(1), 0, s, p);
+    hipLaunchKernelGGL(k_peak_decode, dim3(1), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 

@@ -42,10 +42,11 @@ __global__ __launch_bounds__(kPT) void k_propose(Params p, NetParams net, int us
     __shared__ float xs[kNetIn];
     __shared__ float h1[kNetH], h2[kNetH];
     __shared__ float outs[kNetOut];
+    __shared__ unsigned long long key_s;
     const int t = threadIdx.x;
     int64_t idx = st->forced_idx;
+    const unsigned long long key = collect_peak_key(st, false, &key_s);
     if (idx < 0) {
-        const unsigned long long key = st->peak_key;
         if (key == 0ull) return;     // the fit kernel reports the bad state
         idx = (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
     }
