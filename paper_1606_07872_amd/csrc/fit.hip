@@ -107,7 +107,19 @@ __device__ __forceinline__ void lap(const Params &p, WGShared &S, int slot)
 
 __device__ inline void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
-__device__ __forceinline__ bool wait_publish(FitGlobal *G, WGShared &S)
+// Loads of data another work-group published: agent-scope atomic loads read
+// the coherent copy, so a reader that only needs such data can skip the
+// acquire fence (which would also drop the read-only residual from its L2).
+__device__ inline double ld_shared(const double *q)
+{
+    return __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int32_t ld_shared(const int32_t *q)
+{
+    return __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool wait_publish(FitGlobal *G, WGShared &S, bool acquire = true)
 {
     if (threadIdx.x == 0) {
         unsigned int now = S.gen;
@@ -118,7 +130,7 @@ __device__ __forceinline__ bool wait_publish(FitGlobal *G, WGShared &S)
         }
         S.abort = (now == S.gen) ? 1 : 0;
         S.gen = now;
-        acquire_fence();
+        if (acquire) acquire_fence();
     }
     __syncthreads();
     return S.abort == 0;
@@ -134,7 +146,8 @@ __device__ __forceinline__ void publish(FitGlobal *G)
 }
 
 // Thread 0 waits until *ctr reaches target; returns false on timeout.
-__device__ __forceinline__ bool spin_until(unsigned int *ctr, unsigned int target)
+__device__ __forceinline__ bool spin_until(unsigned int *ctr, unsigned int target,
+                                           bool acquire = true)
 {
     long it = 0;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
@@ -142,7 +155,7 @@ __device__ __forceinline__ bool spin_until(unsigned int *ctr, unsigned int targe
         __builtin_amdgcn_s_sleep(1);
         ++it;
     }
-    acquire_fence();
+    if (acquire) acquire_fence();
     return it < kSpinLimit;
 }
 
@@ -338,15 +351,17 @@ __device__ inline void out_pair(int o, int n, int &i, int &k)
 // Member constants at theta (th_e) and the old members' stored Gaussians
 // (th_old), from the published copy or from work-group 0's own.
 __device__ __forceinline__ void prepare(const Params &p, WGShared &S, int m, const double *th_e,
-                        const double *th_old)
+                                        const double *th_old, bool published = false)
 {
     const int t = threadIdx.x;
     __syncthreads();
     if (t == 0) { S.m = m; S.n = 4 * m; }
     __syncthreads();
     if (t < S.m) {
-        const double a = th_e[4 * t], x = th_e[4 * t + 1], y = th_e[4 * t + 2],
-                     s = th_e[4 * t + 3];
+        // published: another work-group's copy in global memory
+        auto ld = [&](const double *q) { return published ? ld_shared(q) : *q; };
+        const double a = ld(th_e + 4 * t), x = ld(th_e + 4 * t + 1), y = ld(th_e + 4 * t + 2),
+                     s = ld(th_e + 4 * t + 3);
         make_window(x, y, halfwidth(s, p.window_sigmas), p.H, p.W, S.win[t]);
         const double s2 = s * s;
         S.mx[t] = x;
@@ -356,8 +371,8 @@ __device__ __forceinline__ void prepare(const Params &p, WGShared &S, int m, con
         S.minvs2[t] = 1.0 / s2;
         S.minvs3[t] = 1.0 / (s2 * s);
         if (t > 0) {
-            const double oa = th_old[4 * t], ox = th_old[4 * t + 1],
-                         oy = th_old[4 * t + 2], os = th_old[4 * t + 3];
+            const double oa = ld(th_old + 4 * t), ox = ld(th_old + 4 * t + 1),
+                         oy = ld(th_old + 4 * t + 2), os = ld(th_old + 4 * t + 3);
             make_window(ox, oy, halfwidth(os, p.window_sigmas), p.H, p.W, S.wold[t]);
             S.ox[t] = ox;
             S.oy[t] = oy;
@@ -612,13 +627,13 @@ __device__ __forceinline__ double sum_column(const Params &p, int w0, int w1, in
     double v = 0.0;
     int w = w0;
     for (; w + 4 <= w1; w += 4) {
-        const double a = p.partials[(int64_t)w * kPartStride + o];
-        const double b = p.partials[(int64_t)(w + 1) * kPartStride + o];
-        const double c = p.partials[(int64_t)(w + 2) * kPartStride + o];
-        const double d = p.partials[(int64_t)(w + 3) * kPartStride + o];
+        const double a = ld_shared(p.partials + (int64_t)w * kPartStride + o);
+        const double b = ld_shared(p.partials + (int64_t)(w + 1) * kPartStride + o);
+        const double c = ld_shared(p.partials + (int64_t)(w + 2) * kPartStride + o);
+        const double d = ld_shared(p.partials + (int64_t)(w + 3) * kPartStride + o);
         v += a; v += b; v += c; v += d;
     }
-    for (; w < w1; ++w) v += p.partials[(int64_t)w * kPartStride + o];
+    for (; w < w1; ++w) v += ld_shared(p.partials + (int64_t)w * kPartStride + o);
     return v;
 }
 
@@ -1048,7 +1063,8 @@ __device__ inline int eval_groups(int64_t ntiles, int nwg, int min_tiles)
 // Arrival of one work-group after a shared trial (every work-group, every
 // round): the last of a group sums the group's evaluated rows in order into
 // the group row and arrives at the top counter.
-__device__ __forceinline__ void arrive(const Params &p, FitGlobal *G, WGShared &S, int wg, int nwg, int geff)
+__device__ __forceinline__ void arrive(const Params &p, FitGlobal *G, WGShared &S, int wg, int nwg,
+                                       int geff, bool acquire = true)
 {
     const int t = threadIdx.x;
     const int grp = wg / kGroup;
@@ -1056,8 +1072,12 @@ __device__ __forceinline__ void arrive(const Params &p, FitGlobal *G, WGShared &
     const int ng_eval = (geff + kGroup - 1) / kGroup;
     __syncthreads();
     if (t == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(&G->arrive_g[grp], 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
+        // the group rows are read with atomic loads, so the acquire is optional
+        const unsigned prev =
+            acquire ? __hip_atomic_fetch_add(&G->arrive_g[grp], 1u, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT)
+                    : __hip_atomic_fetch_add(&G->arrive_g[grp], 1u, __ATOMIC_RELEASE,
+                                             __HIP_MEMORY_SCOPE_AGENT);
         S.last = (prev == (unsigned)gsize - 1u) ? 1 : 0;
         if (S.last)
             __hip_atomic_store(&G->arrive_g[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1140,10 +1160,11 @@ __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShar
             publish(G);
             evaluate_row(p, S, tile, red, 0, geff, p.partials);
             lap(p, S, kPEval);
-            arrive(p, G, S, 0, nwg, geff);
+            arrive(p, G, S, 0, nwg, geff, false);
             lap(p, S, kPArrive);
             if (t == 0) {
-                S.abort = spin_until(&G->top, (unsigned)ngroups) ? 0 : 1;
+                // the rows are read with atomic loads: no acquire
+                S.abort = spin_until(&G->top, (unsigned)ngroups, false) ? 0 : 1;
                 __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             lap(p, S, kPWait);
@@ -1216,20 +1237,26 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
 
     if (wg != 0) {
         // Workers: evaluate the shared trials work-group 0 publishes.
+        // The residual does not change inside this kernel and everything
+        // published is read with atomic loads, so the workers need no acquire
+        // fence: their L2 keeps the residual's lines from trial to trial.
         for (;;) {
-            if (!wait_publish(G, S)) {
+            if (!wait_publish(G, S, false)) {
                 if (t == 0) st->stop = ASP_ERR_DEVICE;
                 return;
             }
-            if (t == 0) S.done = G->done;
+            if (t == 0) {
+                S.done = ld_shared(&G->done);
+                S.cmd = ld_shared(&G->m);
+            }
             __syncthreads();
             if (S.done) return;
-            prepare(p, S, G->m, G->th_e, G->th_old);
+            prepare(p, S, S.cmd, G->th_e, G->th_old, true);
             const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
             const int geff = eval_groups(ntiles, nwg, p.min_tiles);
             if (wg < geff)
                 evaluate_row(p, S, tile, red, wg, geff, p.partials + (int64_t)wg * kPartStride);
-            arrive(p, G, S, wg, nwg, geff);
+            arrive(p, G, S, wg, nwg, geff, false);
         }
     }
 
@@ -1348,7 +1375,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
             } else if (cmd == kCmdUpdate) {
                 update_tiles(P, rank, T);
             } else if (cmd == kCmdEval) {
-                prepare(P, S, G->m, G->th_e, G->th_old);
+                prepare(P, S, ld_shared(&G->m), G->th_e, G->th_old, true);
                 const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
                 geff = eval_groups(ntiles, T, P.min_tiles);
                 if (rank < geff)
