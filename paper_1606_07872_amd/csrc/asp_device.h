@@ -105,6 +105,7 @@ struct Params {
     int32_t fit_grid;              // work-groups of the fit kernel
     int32_t solo_tiles;            // trials of at most this many tiles: work-group 0 alone
     int32_t min_tiles;             // least tiles per work-group in a shared trial
+    unsigned long long spin_ticks; // time bound of every wait between work-groups
     FitGlobal *fg;
     double *partials;              // fit_grid x kPartStride
     // recording of (patch, target) training pairs; rec_cap = 0 disables
@@ -211,6 +212,7 @@ struct BatchArgs {
     int64_t n_iter;                // iterations per field in this launch
     int64_t solo_peak_px;          // peak search by the leader alone up to this many pixels
     int64_t solo_update_px;        // update by the leader alone up to this bounding box
+    unsigned long long spin_ticks; // time bound of every wait between work-groups
     int32_t n_fields, team_size, solo_tiles, min_tiles;
 };
 int batch_grid_size(int device);

@@ -34,8 +34,7 @@ constexpr int kT = kFitThreads;
 constexpr int kOwnMax = (kNOutMax + kT - 1) / kT;
 constexpr size_t kTileBytes = sizeof(float) * kT * kTileStride;
 constexpr size_t kMatBytes = sizeof(double) * kMaxN * kMaxN;
-constexpr size_t kFitLds = kTileBytes + 2 * kMatBytes;   // tile (or A) | He | Hc
-constexpr long kSpinLimit = 1L << 22;
+constexpr size_t kFitLds = kTileBytes + 2 * kMatBytes;   // tile (or A) | two Gram buffers
 constexpr int kGroup = 16;        // work-groups per first-level arrival group
 static_assert(kTileBytes >= kMatBytes, "A shares the tile buffer");
 
@@ -71,6 +70,7 @@ struct WGShared {
     double t0[4];                  // the simple start of the new component
     double alt[4];                 // a proposal start, compared with t0 by the objective
     int32_t alt_pending, chose_prop;
+    int32_t hsel;                  // which of the two Gram buffers holds the current point
     double sel[2];                 // peak pixel (x, y): the active set is selected around it
     int32_t nch, sel_done;
     unsigned long long key;        // the peak key of this fit (collect_peak_key)
@@ -119,13 +119,16 @@ __device__ inline int32_t ld_shared(const int32_t *q)
     return __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ bool wait_publish(FitGlobal *G, WGShared &S, bool acquire = true)
+// Every wait is bounded in time: `limit` device wall-clock ticks.
+__device__ __forceinline__ bool wait_publish(FitGlobal *G, WGShared &S, unsigned long long limit,
+                                             bool acquire = true)
 {
     if (threadIdx.x == 0) {
         unsigned int now = S.gen;
-        for (long it = 0; it < kSpinLimit; ++it) {
+        const unsigned long long t0 = now_ticks();
+        for (;;) {
             now = __hip_atomic_load(&G->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (now != S.gen) break;
+            if (now != S.gen || now_ticks() - t0 > limit) break;
             __builtin_amdgcn_s_sleep(1);
         }
         S.abort = (now == S.gen) ? 1 : 0;
@@ -147,16 +150,16 @@ __device__ __forceinline__ void publish(FitGlobal *G)
 
 // Thread 0 waits until *ctr reaches target; returns false on timeout.
 __device__ __forceinline__ bool spin_until(unsigned int *ctr, unsigned int target,
-                                           bool acquire = true)
+                                           unsigned long long limit, bool acquire = true)
 {
-    long it = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
-           it < kSpinLimit) {
+    const unsigned long long t0 = now_ticks();
+    bool ok = true;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (now_ticks() - t0 > limit) { ok = false; break; }
         __builtin_amdgcn_s_sleep(1);
-        ++it;
     }
     if (acquire) acquire_fence();
-    return it < kSpinLimit;
+    return ok;
 }
 
 // ---------------------------------------------------------------------------
@@ -284,6 +287,7 @@ __device__ __forceinline__ void setup_fit(const Params &p, FitGlobal *G, WGShare
     const int m = 1 + S.nch;
     if (t == 0) {
         S.members[0] = -1;
+        S.hsel = 0;
         S.m = m;
         S.n = 4 * m;
         S.phase = 0;
@@ -781,15 +785,8 @@ __device__ __forceinline__ void lm_accept(const Params &p, WGShared &S)
 // triangle in registers: the same arithmetic as the work-group path below,
 // with each Cholesky column scaled by one reciprocal square root.
 template <int N>
-__device__ __forceinline__ void lm_solve_small(int32_t lm_max_iter, WGShared &S, const double *He,
-                                               double *Hc)
+__device__ __forceinline__ void lm_solve_small(int32_t lm_max_iter, WGShared &S, const double *Hc)
 {
-    if (S.accept) {
-        for (int e = 0; e < N * N; ++e) Hc[e] = He[e];
-#pragma unroll
-        for (int i = 0; i < N; ++i) { S.th_c[i] = S.th_e[i]; S.g_c[i] = S.ge[i]; }
-        S.F_c = S.Fe; S.chi2_c = S.chi2e; S.npx_c = S.npx_e;
-    }
     double dmax = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) dmax = Hc[i * N + i] > dmax ? Hc[i * N + i] : dmax;
@@ -815,11 +812,13 @@ __device__ __forceinline__ void lm_solve_small(int32_t lm_max_iter, WGShared &S,
                 a[i][k] = (fr[i] || fr[k]) ? (i == k ? 1.0 : 0.0)
                                            : Hc[i * N + k] + (i == k ? mu * dd[i] : 0.0);
         bool ok = true;
+        double rinv[N];                  // 1 / L_kk
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const double d = a[k][k];
             ok = ok && d > 0.0 && isfinite(d);
             const double r = ok ? 1.0 / sqrt(d) : 0.0;
+            rinv[k] = r;
             a[k][k] = ok ? d * r : 1.0;
 #pragma unroll
             for (int i = k + 1; i < N; ++i) a[i][k] *= r;
@@ -835,14 +834,14 @@ __device__ __forceinline__ void lm_solve_small(int32_t lm_max_iter, WGShared &S,
                 double v = rhs[i];
 #pragma unroll
                 for (int j = 0; j < i; ++j) v -= a[i][j] * x[j];
-                x[i] = v / a[i][i];
+                x[i] = v * rinv[i];
             }
 #pragma unroll
             for (int i = N - 1; i >= 0; --i) {
                 double v = x[i];
 #pragma unroll
                 for (int j = i + 1; j < N; ++j) v -= a[j][i] * x[j];
-                x[i] = v / a[i][i];
+                x[i] = v * rinv[i];
             }
 #pragma unroll
             for (int i = 0; i < N; ++i) ok = ok && isfinite(x[i]);
@@ -868,49 +867,47 @@ __device__ __forceinline__ void lm_solve_small(int32_t lm_max_iter, WGShared &S,
     }
 }
 
-__device__ __forceinline__ void lm_step(const Params &p, WGShared &S, double *He, double *Hc, double *A)
+__device__ __forceinline__ void lm_step(const Params &p, WGShared &S, double *H2, double *A)
 {
     const int t = threadIdx.x;
     const int n = S.n;
     if (t == 0) lm_accept(p, S);
     __syncthreads();
-    if (S.phase == 2) {
-        // the simple start is evaluated (and accepted); the next evaluation
-        // is the proposal start with the other members unchanged
-        for (int e = t; e < n * n; e += kT) Hc[e] = He[e];
-        if (t < n) {
-            S.th_c[t] = S.th_e[t];
-            S.g_c[t] = S.ge[t];
-            if (t < 4) {
-                double v = S.alt[t];
-                if (!(v >= S.lo[t])) v = S.lo[t];
-                if (v > S.hi[t]) v = S.hi[t];
-                S.th_e[t] = v;
-            }
-        }
+    if (S.accept) {
+        // the evaluated point becomes the current one; its Gram matrix buffer
+        // becomes the current buffer (no copy)
+        if (t < n) { S.th_c[t] = S.th_e[t]; S.g_c[t] = S.ge[t]; }
         if (t == 0) {
             S.F_c = S.Fe; S.chi2_c = S.chi2e; S.npx_c = S.npx_e;
+            S.hsel ^= 1;
+        }
+    }
+    __syncthreads();
+    if (S.phase == 2) {
+        // the simple start is evaluated; the next evaluation is the proposal
+        // start with the other members unchanged
+        if (t < 4) {
+            double v = S.alt[t];
+            if (!(v >= S.lo[t])) v = S.lo[t];
+            if (v > S.hi[t]) v = S.hi[t];
+            S.th_e[t] = v;
+        }
+        if (t == 0) {
             S.alt_pending = 0;
             S.finished = 0;
         }
         __syncthreads();
         return;
     }
+    const double *Hc = H2 + S.hsel * (kMaxN * kMaxN);
     if (n <= 8) {
         if (t == 0) {
-            if (n == 4) lm_solve_small<4>(p.lm_max_iter, S, He, Hc);
-            else lm_solve_small<8>(p.lm_max_iter, S, He, Hc);
+            if (n == 4) lm_solve_small<4>(p.lm_max_iter, S, Hc);
+            else lm_solve_small<8>(p.lm_max_iter, S, Hc);
         }
         __syncthreads();
         return;
     }
-    __syncthreads();
-    if (S.accept) {
-        for (int e = t; e < n * n; e += kT) Hc[e] = He[e];
-        if (t < n) { S.th_c[t] = S.th_e[t]; S.g_c[t] = S.ge[t]; }
-        if (t == 0) { S.F_c = S.Fe; S.chi2_c = S.chi2e; S.npx_c = S.npx_e; }
-    }
-    __syncthreads();
     for (;;) {
         __syncthreads();
         if (S.finished) break;
@@ -1131,7 +1128,7 @@ __device__ __forceinline__ void fit_begin(const Params &p, WGShared &S, bool abo
 // work-groups.  Returns false when a wait ran out; the context is then marked
 // with ASP_ERR_DEVICE.
 __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShared &S, float *tile,
-                                           double *red, double *A, double *He, double *Hc,
+                                           double *red, double *A, double *H2,
                                            int nwg, int cmd)
 {
     DevState *st = p.st;
@@ -1149,7 +1146,7 @@ __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShar
             // small: the leading work-group alone, no publication
             evaluate_row(p, S, tile, red, 0, 1, p.partials);
             lap(p, S, kPEval);
-            reduce_partials(p, S, 0, 1, He);
+            reduce_partials(p, S, 0, 1, H2 + (1 - S.hsel) * (kMaxN * kMaxN));
             lap(p, S, kPReduce);
         } else {
             // large: every work-group takes a share
@@ -1164,7 +1161,7 @@ __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShar
             lap(p, S, kPArrive);
             if (t == 0) {
                 // the rows are read with atomic loads: no acquire
-                S.abort = spin_until(&G->top, (unsigned)ngroups, false) ? 0 : 1;
+                S.abort = spin_until(&G->top, (unsigned)ngroups, p.spin_ticks, false) ? 0 : 1;
                 __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             lap(p, S, kPWait);
@@ -1174,11 +1171,12 @@ __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShar
                 __syncthreads();
                 return false;
             }
+            double *He = H2 + (1 - S.hsel) * (kMaxN * kMaxN);   // the trial's buffer
             if (ng_eval > 1) reduce_partials(p, S, nwg, nwg + ng_eval, He);
             else reduce_partials(p, S, 0, geff, He);
             lap(p, S, kPReduce);
         }
-        lm_step(p, S, He, Hc, A);
+        lm_step(p, S, H2, A);
         lap(p, S, kPLmStep);
         if (t == 0) {
             const unsigned long long npx = (unsigned long long)S.npx_e;
@@ -1212,8 +1210,7 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
     extern __shared__ __align__(16) unsigned char lds[];
     float *tile = reinterpret_cast<float *>(lds);
     double *A = reinterpret_cast<double *>(lds);               // shares the tile buffer
-    double *He = reinterpret_cast<double *>(lds + kTileBytes);
-    double *Hc = He + kMaxN * kMaxN;
+    double *H2 = reinterpret_cast<double *>(lds + kTileBytes);   // two Gram buffers
     __shared__ WGShared S;
     __shared__ double red[kT];
     FitGlobal *G = p.fg;
@@ -1241,7 +1238,7 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
         // published is read with atomic loads, so the workers need no acquire
         // fence: their L2 keeps the residual's lines from trial to trial.
         for (;;) {
-            if (!wait_publish(G, S, false)) {
+            if (!wait_publish(G, S, p.spin_ticks, false)) {
                 if (t == 0) st->stop = ASP_ERR_DEVICE;
                 return;
             }
@@ -1262,7 +1259,7 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
 
     // Work-group 0 drives the fit.
     if (t == 0) {
-        S.abort = spin_until(&G->top, (unsigned)nwg) ? 0 : 1;
+        S.abort = spin_until(&G->top, (unsigned)nwg, p.spin_ticks) ? 0 : 1;
         __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         lap(p, S, kPCheckin);
     }
@@ -1275,7 +1272,7 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
     }
     __syncthreads();
     if (!S.stop) {
-        fit_trials(p, G, S, tile, red, A, He, Hc, nwg, 0);
+        fit_trials(p, G, S, tile, red, A, H2, nwg, 0);
         if (t == 0) G->done = 1;
     }
     publish(G);
@@ -1313,10 +1310,11 @@ __device__ __forceinline__ void load_field(const BatchArgs &b, int f, FitGlobal 
 }
 
 // The leader's wait for the team's arrivals; false when it ran out.
-__device__ __forceinline__ bool team_wait(FitGlobal *G, WGShared &S, int ngroups)
+__device__ __forceinline__ bool team_wait(FitGlobal *G, WGShared &S, int ngroups,
+                                          unsigned long long limit)
 {
     if (threadIdx.x == 0) {
-        S.abort = spin_until(&G->top, (unsigned)ngroups) ? 0 : 1;
+        S.abort = spin_until(&G->top, (unsigned)ngroups, limit) ? 0 : 1;
         __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
@@ -1328,8 +1326,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
     extern __shared__ __align__(16) unsigned char lds[];
     float *tile = reinterpret_cast<float *>(lds);
     double *A = reinterpret_cast<double *>(lds);
-    double *He = reinterpret_cast<double *>(lds + kTileBytes);
-    double *Hc = He + kMaxN * kMaxN;
+    double *H2 = reinterpret_cast<double *>(lds + kTileBytes);   // two Gram buffers
     __shared__ WGShared S;
     __shared__ double red[kT];
     __shared__ Params P;
@@ -1356,7 +1353,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
 
     if (rank != 0) {
         for (;;) {
-            if (!wait_publish(G, S)) return;      // the leader marks its field
+            if (!wait_publish(G, S, b.spin_ticks)) return;      // the leader marks its field
             if (t == 0) {
                 S.cmd = G->cmd;
                 S.fld = G->field;
@@ -1388,7 +1385,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
 
     // the leader
     if (t == 0) {
-        if (T > 1) S.abort = spin_until(&G->top, (unsigned)(T - 1)) ? 0 : 1;
+        if (T > 1) S.abort = spin_until(&G->top, (unsigned)(T - 1), b.spin_ticks) ? 0 : 1;
         __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
@@ -1419,7 +1416,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
                 publish(G);
                 peak_scan(P.R, npx, 0u, (uint32_t)T, P.st);
                 arrive(P, G, S, 0, T, 0);
-                if (!team_wait(G, S, ngroups)) { ok = false; break; }
+                if (!team_wait(G, S, ngroups, b.spin_ticks)) { ok = false; break; }
             }
             __syncthreads();
             // the stop test and the fit (Sect. 2 step 4; Sect. 3)
@@ -1427,7 +1424,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
             if (t == 0) fit_begin(P, S, false);
             __syncthreads();
             if (S.stop) break;
-            if (!fit_trials(P, G, S, tile, red, A, He, Hc, T, kCmdEval)) { ok = false; break; }
+            if (!fit_trials(P, G, S, tile, red, A, H2, T, kCmdEval)) { ok = false; break; }
             // the residual update (Sect. 2 step 3)
             if (t == 0) {
                 const int32_t *bb = P.st->bb;
@@ -1441,7 +1438,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
                 publish(G);
                 update_tiles(P, 0, T);
                 arrive(P, G, S, 0, T, 0);
-                if (!team_wait(G, S, ngroups)) { ok = false; break; }
+                if (!team_wait(G, S, ngroups, b.spin_ticks)) { ok = false; break; }
             }
         }
     }

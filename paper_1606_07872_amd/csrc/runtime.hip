@@ -102,6 +102,16 @@ asp_status pull_all(asp_ctx *c) { return pull_state(c, 0, sizeof(DevState)); }
 
 bool fit_setup_done = false;
 
+// Waits between work-groups end after 2 s of device wall clock.
+unsigned long long spin_limit_ticks(int device)
+{
+    int rate_khz = 100000;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+        rate_khz <= 0)
+        rate_khz = 100000;
+    return (unsigned long long)rate_khz * 2000ull;
+}
+
 asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t W,
                          const float *psf, bool psf_dev, int64_t Hp, int64_t Wp, float gain,
                          float threshold, const asp_options *opt_in, asp_ctx **out)
@@ -228,6 +238,7 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     P.fit_grid = fit_grid;
     P.solo_tiles = opt.fit_solo_tiles == 0 ? 8 : opt.fit_solo_tiles;
     P.min_tiles = opt.fit_min_tiles == 0 ? 2 : opt.fit_min_tiles;
+    P.spin_ticks = spin_limit_ticks(c->device);
     P.fg = c->fg;
     P.partials = c->partials;
     *out = c;
@@ -734,6 +745,7 @@ asp_status batch_capture(asp_batch *b, int64_t n_iter)
     a.partials = b->d_partials;
     a.n_iter = n_iter;
     a.solo_peak_px = b->solo_peak_px;
+    a.spin_ticks = spin_limit_ticks(b->device);
     a.solo_update_px = b->solo_update_px;
     a.n_fields = (int32_t)b->ctx.size();
     a.team_size = b->team;
