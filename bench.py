@@ -212,6 +212,7 @@ def main():
                     help="time without the per-launch event pairs")
     ap.add_argument("--solo-tiles", type=int, default=0)
     ap.add_argument("--min-tiles", type=int, default=0)
+    ap.add_argument("--group", type=int, default=0, help="work-groups per arrival counter")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--no-learned", action="store_true",
@@ -255,7 +256,7 @@ def main():
     total = args.warmup + args.steps
     ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=max(f.max_iter, total),
                       max_active=f.max_active, fit_solo_tiles=args.solo_tiles,
-                      fit_min_tiles=args.min_tiles)
+                      fit_min_tiles=args.min_tiles, fit_group=args.group)
     del d_dirty, d_psf
     torch.cuda.synchronize()
     ctx.run(args.warmup)

@@ -111,6 +111,9 @@ typedef struct {
                                     0 = default (8), -1 = never                  */
     int32_t fit_min_tiles;       /* least tiles per work-group when a trial is
                                     shared over the GPU; 0 = default (2)         */
+    int32_t fit_group;           /* work-groups per first-level arrival counter of
+                                    a shared trial; 0 = default (16)             */
+    int32_t pad0;
     double window_sigmas;        /* window half-width factor c_w; default 5      */
     double max_width;            /* upper bound on s; 0 = max(omega_b, min(H,W)/8) */
     double lm_mu0;               /* initial damping; default 1e-3                */

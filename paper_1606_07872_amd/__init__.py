@@ -47,6 +47,7 @@ class Options(ctypes.Structure):
                 ("max_active", ctypes.c_int32), ("lm_max_iter", ctypes.c_int32),
                 ("init_mode", ctypes.c_int32), ("capacity", ctypes.c_int32),
                 ("fit_solo_tiles", ctypes.c_int32), ("fit_min_tiles", ctypes.c_int32),
+                ("fit_group", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("window_sigmas", ctypes.c_double), ("max_width", ctypes.c_double),
                 ("lm_mu0", ctypes.c_double), ("lm_tol", ctypes.c_double),
                 ("psf_lobe_frac", ctypes.c_double), ("stream", ctypes.c_void_p)]

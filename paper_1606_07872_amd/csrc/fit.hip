@@ -1064,9 +1064,10 @@ __device__ __forceinline__ void arrive(const Params &p, FitGlobal *G, WGShared &
                                        int geff, bool acquire = true)
 {
     const int t = threadIdx.x;
-    const int grp = wg / kGroup;
-    const int gsize = (grp + 1) * kGroup < nwg ? kGroup : nwg - grp * kGroup;
-    const int ng_eval = (geff + kGroup - 1) / kGroup;
+    const int gs = p.group;
+    const int grp = wg / gs;
+    const int gsize = (grp + 1) * gs < nwg ? gs : nwg - grp * gs;
+    const int ng_eval = (geff + gs - 1) / gs;
     __syncthreads();
     if (t == 0) {
         // the group rows are read with atomic loads, so the acquire is optional
@@ -1081,7 +1082,7 @@ __device__ __forceinline__ void arrive(const Params &p, FitGlobal *G, WGShared &
     }
     __syncthreads();
     if (!S.last) return;
-    const int r0 = grp * kGroup, r1 = (r0 + kGroup < geff) ? r0 + kGroup : geff;
+    const int r0 = grp * gs, r1 = (r0 + gs < geff) ? r0 + gs : geff;
     if (ng_eval > 1 && r0 < r1) sum_rows(p, S.n, r0, r1, nwg + grp);
     __syncthreads();
     if (t == 0) __hip_atomic_fetch_add(&G->top, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1133,7 +1134,7 @@ __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShar
 {
     DevState *st = p.st;
     const int t = threadIdx.x;
-    const int ngroups = (nwg + kGroup - 1) / kGroup;
+    const int ngroups = (nwg + p.group - 1) / p.group;
     mark(S);
     setup_fit(p, G, S, S.use_prop != 0);
     lap(p, S, kPSetup);
@@ -1151,7 +1152,7 @@ __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShar
         } else {
             // large: every work-group takes a share
             const int geff = eval_groups(ntiles, nwg, p.min_tiles);
-            const int ng_eval = (geff + kGroup - 1) / kGroup;
+            const int ng_eval = (geff + p.group - 1) / p.group;
             if (t < S.n) G->th_e[t] = S.th_e[t];
             if (t == 0 && cmd) G->cmd = cmd;
             publish(G);
@@ -1305,6 +1306,7 @@ __device__ __forceinline__ void load_field(const BatchArgs &b, int f, FitGlobal 
         P.partials = parts;
         P.solo_tiles = b.team_size == 1 ? 0x7FFFFFFF : b.solo_tiles;
         P.min_tiles = b.min_tiles;
+        P.group = kGroup;
     }
     __syncthreads();
 }

@@ -130,7 +130,7 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     }
     if (opt.max_iter < 0 || opt.max_active < 1 || opt.max_active > ASP_MAX_ACTIVE ||
         opt.lm_max_iter < 1 || opt.init_mode < 0 || opt.init_mode > 1 || opt.capacity < 0 ||
-        opt.fit_solo_tiles < -1 || opt.fit_min_tiles < 0 ||
+        opt.fit_solo_tiles < -1 || opt.fit_min_tiles < 0 || opt.fit_group < 0 ||
         !(opt.window_sigmas > 0.0) || !(opt.max_width >= 0.0) || !(opt.lm_mu0 > 0.0) ||
         !(opt.lm_tol > 0.0) || !(opt.psf_lobe_frac > 0.0 && opt.psf_lobe_frac < 1.0))
         return ASP_ERR_INVALID_ARG;
@@ -239,6 +239,11 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     P.solo_tiles = opt.fit_solo_tiles == 0 ? 8 : opt.fit_solo_tiles;
     P.min_tiles = opt.fit_min_tiles == 0 ? 2 : opt.fit_min_tiles;
     P.spin_ticks = spin_limit_ticks(c->device);
+    P.group = opt.fit_group == 0 ? 16 : opt.fit_group;
+    if ((fit_grid + P.group - 1) / P.group > asp::kMaxGroups) {
+        c->err = "fit_group too small for the grid";
+        return bail(ASP_ERR_INVALID_ARG);
+    }
     P.fg = c->fg;
     P.partials = c->partials;
     *out = c;
