@@ -540,18 +540,20 @@ __device__ __forceinline__ void evaluate_tiles(const Params &p, WGShared &S, flo
 }
 
 // The same partial for fits of at most two members (n <= 8): each thread keeps
-// the 15 or 45 Gram entries of its own pixels in registers, Kahan-compensated,
-// with no barrier per tile; the threads' sums are combined once at the end by
-// wave shuffles and the four waves in order.
+// the 15 or 45 Gram entries of its own pixels in registers, with no barrier per
+// tile.  J and r are FP32 values; their products are exact in FP64 and are
+// accumulated there (one FP64 FMA per entry, half the work of a Kahan update
+// in FP32 on this hardware and a smaller error).  The threads' sums are
+// combined once at the end by wave shuffles and the four waves in order.
 template <int M>
 __device__ __forceinline__ void evaluate_tiles_reg(const Params &p, WGShared &S, int64_t tile0, int64_t stride,
                                    double *out)
 {
     constexpr int N = 4 * M, C = N + 1, NO = C * (C + 1) / 2;
     const int t = threadIdx.x;
-    float acc_s[NO], acc_c[NO];
+    double acc[NO];
 #pragma unroll
-    for (int o = 0; o < NO; ++o) { acc_s[o] = 0.0f; acc_c[o] = 0.0f; }
+    for (int o = 0; o < NO; ++o) acc[o] = 0.0;
     double npx = 0.0, f_acc = 0.0, c_acc = 0.0;
     const int64_t total = S.pref[M];
     const int64_t ntiles = (total + kT - 1) / kT;
@@ -593,21 +595,19 @@ __device__ __forceinline__ void evaluate_tiles_reg(const Params &p, WGShared &S,
         col[N] = (float)res;
         f_acc += Mv * (Mv - 2.0 * D);
         c_acc += res * res;
+        double cold[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) cold[i] = (double)col[i];
         int o = 0;
 #pragma unroll
         for (int i = 0; i < C; ++i)
 #pragma unroll
-            for (int k = i; k < C; ++k, ++o) {
-                const float y = col[i] * col[k] - acc_c[o];
-                const float tt = acc_s[o] + y;
-                acc_c[o] = (tt - acc_s[o]) - y;
-                acc_s[o] = tt;
-            }
+            for (int k = i; k < C; ++k, ++o) acc[o] = fma(cold[i], cold[k], acc[o]);
     }
     const int lane = t & 63, wave = t >> 6;
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-        const double v = wave_sum((double)acc_s[o] - (double)acc_c[o]);
+        const double v = wave_sum(acc[o]);
         if (lane == 0) S.wred[wave][o] = v;
     }
     const double f_w = wave_sum(f_acc), c_w = wave_sum(c_acc), p_w = wave_sum(npx);
