@@ -2,9 +2,10 @@
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg
 may import this package.  It is independent of the HIP library: the minor cycle
-lives in plain C (``asp_oracle.c``, FP64, no fused multiply-add), and the MLP
-of the learned proposal in NumPy FP64 (``mlp.py``).  This module only marshals
-arguments to the C code.
+lives in plain C (``asp_oracle.c``, FP64, no fused multiply-add), the MLP of
+the learned proposal in NumPy FP64 (``mlp.py``), and the smoothing initial
+values with their switch in NumPy/SciPy FP64 (``smoothing.py``).  This module
+marshals arguments to the C code and drives the switch.
 """
 from __future__ import annotations
 
@@ -91,6 +92,8 @@ def lib():
         L.orc_cholesky_solve.argtypes = [ctypes.c_int, dp, dp, dp]
         L.orc_step.argtypes = [ctypes.POINTER(_State), ctypes.c_void_p, ctypes.POINTER(_Report),
                                ctypes.c_void_p]
+        L.orc_step_start.argtypes = [ctypes.POINTER(_State), dp, ctypes.POINTER(_Report),
+                                     ctypes.c_void_p]
         L.orc_run.argtypes = [ctypes.POINTER(_State), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         L.orc_residual_from_scratch.argtypes = [ctypes.POINTER(_State), dp, dp]
         L.orc_fit_gaussians.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp,
@@ -177,7 +180,8 @@ class Oracle:
 
     def __init__(self, dirty, psf=None, *, gain=0.1, threshold=0.0, max_iter=1000,
                  max_active=5, cap=None, alpha_b=None, omega_b=None, lm_max_iter=100,
-                 window_sigmas=5.0, lm_tol=1e-5, max_width=0.0):
+                 window_sigmas=5.0, lm_tol=1e-5, max_width=0.0, smooth_scales=0,
+                 smooth_norm="peak", switch_deconvolved=False):
         L = lib()
         self.dirty = np.ascontiguousarray(dirty, dtype=np.float64)
         H, W = self.dirty.shape
@@ -197,6 +201,24 @@ class Oracle:
         st.comps = self.comps_buf.ctypes.data
         st.L, st.cap, st.k = 0, cap, 0
         self.st = st
+        # the smoothing method and its switch (Sect. 2 step 1, Sect. 3);
+        # smooth_scales = 0 keeps the simple method in every iteration
+        self.smooth_scales = int(smooth_scales)
+        self.smooth_norm = smooth_norm
+        self.switch_deconvolved = bool(switch_deconvolved)
+        self.smooth_now = self.smooth_scales > 0
+
+    @property
+    def s_max(self) -> float:
+        st = self.st
+        m = st.max_width if st.max_width > 0.0 else min(st.H, st.W) / 8.0
+        return max(m, st.omega_b)
+
+    def smooth_best(self, method=None) -> dict:
+        """The smoothing method's peak and start values on the current residual."""
+        from . import smoothing
+        return smoothing.best(self.R, self.st.omega_b, max(1, self.smooth_scales), self.s_max,
+                              self.st.window_sigmas, method, self.smooth_norm)
 
     # -- state ------------------------------------------------------------
     @property
@@ -236,15 +258,30 @@ class Oracle:
         self.st.k = int(k)
 
     # -- the iteration ----------------------------------------------------
-    def step(self, init=None, want_hess=False) -> dict:
+    def step(self, init=None, want_hess=False, start=None, smooth=None) -> dict:
+        """One iteration.  init: a proposal (learned mode).  With the smoothing
+        method on, ``smooth`` (default: the switch's state) says whether this
+        iteration smooths; ``start`` overrides the smoothing start values (a
+        caller that checked a near-tie passes the other side's choice)."""
+        from . import smoothing
         rep = _Report()
         hess = np.zeros((4 * MAX_ACTIVE) ** 2) if want_hess else None
-        ip = None
-        if init is not None:
-            init_arr = np.ascontiguousarray(np.asarray(init, dtype=np.float64))
-            ip = init_arr.ctypes.data
-        rc = lib().orc_step(ctypes.byref(self.st), ip, ctypes.byref(rep),
-                            None if hess is None else hess.ctypes.data)
+        hp = None if hess is None else hess.ctypes.data
+        use_smooth = self.smooth_now if smooth is None else bool(smooth)
+        sb = None
+        if self.smooth_scales > 0 and use_smooth and init is None:
+            if start is None:
+                sb = self.smooth_best()
+                start = sb["start"]
+            st4 = np.ascontiguousarray(np.asarray(start, dtype=np.float64))
+            rc = lib().orc_step_start(ctypes.byref(self.st), st4, ctypes.byref(rep), hp)
+        else:
+            use_smooth = False
+            ip = None
+            if init is not None:
+                init_arr = np.ascontiguousarray(np.asarray(init, dtype=np.float64))
+                ip = init_arr.ctypes.data
+            rc = lib().orc_step(ctypes.byref(self.st), ip, ctypes.byref(rep), hp)
         m = rep.n_active
         out = {"status": rc, "idx": int(rep.idx), "peak": rep.peak, "n_active": m,
                "members": list(rep.members[:m]), "lm_iters": rep.lm_iters,
@@ -257,9 +294,25 @@ class Oracle:
         if want_hess and m:
             n = 4 * m
             out["hess"] = hess[: n * n].reshape(n, n).copy()
+        out["smoothed"] = use_smooth
+        if sb is not None:
+            out["smooth"] = {k: sb[k] for k in ("scale", "idx", "sigma", "score", "corr", "norm2")}
+        if self.smooth_scales > 0 and rc in (ORC_OK, ORC_LM_NOT_CONVERGED):
+            # the switch for the next iteration, from the new component's start
+            # width and fitted width
+            self.smooth_now = not smoothing.simple_next(
+                float(out["theta"][0, 3]), float(out["theta0"][0, 3]), self.st.omega_b,
+                self.switch_deconvolved)
         return out
 
     def run(self, n_iter: int):
+        if self.smooth_scales > 0:
+            rc, i = ORC_OK, 0
+            for i in range(n_iter):
+                rc = self.step()["status"]
+                if rc not in (ORC_OK, ORC_LM_NOT_CONVERGED):
+                    return rc, i
+            return rc, n_iter
         done = ctypes.c_int64()
         rc = lib().orc_run(ctypes.byref(self.st), n_iter, ctypes.byref(done))
         return rc, done.value

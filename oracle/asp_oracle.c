@@ -633,7 +633,8 @@ static void add_window(orc_state *st, double a, double x, double y, double s, do
     *touched += (w[1] - w[0] + 1) * (w[3] - w[2] + 1);
 }
 
-int orc_step(orc_state *st, const double *init, orc_report *rep, double *hess_out)
+static int step_impl(orc_state *st, const double *init, const double *start4, orc_report *rep,
+                     double *hess_out)
 {
     memset(rep, 0, sizeof *rep);
     int64_t n = st->H * st->W;
@@ -652,7 +653,13 @@ int orc_step(orc_state *st, const double *init, orc_report *rep, double *hess_ou
     double theta[4 * ORC_MAX_ACTIVE];
     lm_result lmr;
     int used_fallback = 0, rc;
-    if (init) {
+    if (start4) {
+        /* Start values found elsewhere (the smoothing method of Sect. 2 step 1
+         * and Sect. 3): the new component starts there, and the active set is
+         * selected around that start, as it is around the simple start. */
+        rc = fit_from(st, start4, start4, NULL, NULL, rep, theta, &lmr, hess_out);
+        if (rc != ORC_OK) return rep->status = rc;
+    } else if (init) {
         /* A proposal: width at least omega_b, centre within 16 px of the peak. */
         double p4[4] = {init[0], init[1], init[2], init[3]};
         if (!(p4[0] * pv > 0.0)) p4[0] = pv;     /* the peak's sign; also NaN */
@@ -714,6 +721,17 @@ int orc_step(orc_state *st, const double *init, orc_report *rep, double *hess_ou
     rep->update_px = touched;
     rep->status = lmr.converged ? ORC_OK : ORC_LM_NOT_CONVERGED;
     return rep->status;
+}
+
+int orc_step(orc_state *st, const double *init, orc_report *rep, double *hess_out)
+{
+    return step_impl(st, init, NULL, rep, hess_out);
+}
+
+int orc_step_start(orc_state *st, const double *start4, orc_report *rep, double *hess_out)
+{
+    if (!start4) return ORC_ERR_ARG;
+    return step_impl(st, NULL, start4, rep, hess_out);
 }
 
 int orc_run(orc_state *st, int64_t n_iter, int64_t *done)

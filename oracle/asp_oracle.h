@@ -110,6 +110,13 @@ int orc_cholesky_solve(int n, const double *A, const double *b, double *x);
  * (nullable) receives the final J^T J (n x n, n = 4 * n_active). */
 int orc_step(orc_state *st, const double *init, orc_report *rep, double *hess_out);
 
+/* One iteration whose new component starts at start4 = (a, x, y, s), the
+ * start values of the smoothing method (Sect. 2 step 1, Sect. 3), computed by
+ * the caller.  The peak and the stop test are those of orc_step; the active
+ * set is selected around start4 (sign of a, window of half-width h(s) around
+ * (x, y), co-location radius max(omega_b, min(s_j, s))); no fallback. */
+int orc_step_start(orc_state *st, const double *start4, orc_report *rep, double *hess_out);
+
 /* Up to n_iter iterations of orc_step with the simple initial values; returns
  * the last status and the number of iterations done. */
 int orc_run(orc_state *st, int64_t n_iter, int64_t *done);
