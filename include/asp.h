@@ -92,11 +92,13 @@ typedef struct {
     double theta0[4 * ASP_MAX_ACTIVE];   /* start (a, x, y, s) per member        */
     double theta[4 * ASP_MAX_ACTIVE];    /* fitted, before the loop gain         */
     int64_t fit_px;              /* pixels in the union of windows at the fit    */
-    int32_t init_source;         /* proposal considered: 0 none (simple values),
-                                    1 the caller's init, 2 the network           */
+    int32_t init_source;         /* start values: 0 the simple values, 1 the
+                                    caller's init, 2 the network, 3 the smoothing
+                                    method (init holds its start)                */
     int32_t start_from_proposal; /* 1: the proposal scored a lower objective than
                                     the simple values and LM started from it     */
-    double init[4];              /* the proposal (a, x, y, s) before clamping     */
+    double init[4];              /* the proposal (a, x, y, s) before clamping, or
+                                    the smoothing method's start                 */
 } asp_fit_report;
 
 typedef struct {
@@ -104,7 +106,8 @@ typedef struct {
     int32_t max_iter;            /* iteration count stop; default 1000           */
     int32_t max_active;          /* K_max, 1..ASP_MAX_ACTIVE; default 5          */
     int32_t lm_max_iter;         /* LM trial budget; default 100                 */
-    int32_t init_mode;           /* 0 simple initial values, 1 learned proposal  */
+    int32_t init_mode;           /* 0 simple initial values, 1 learned proposal,
+                                    2 the smoothing method with the 5 % switch  */
     int32_t capacity;            /* component list size; 0 = max_iter            */
     int32_t fit_solo_tiles;      /* LM trials over at most this many 256-pixel
                                     tiles are evaluated by one work-group;
@@ -113,7 +116,15 @@ typedef struct {
                                     shared over the GPU; 0 = default (2)         */
     int32_t fit_group;           /* work-groups per first-level arrival counter of
                                     a shared trial; 0 = default (16)             */
-    int32_t pad0;
+    int32_t smooth_scales;       /* trial widths omega_b 2^j, j < smooth_scales,
+                                    of the smoothing method, 1..ASP_MAX_SCALES;
+                                    0 = default (5)                              */
+    int32_t smooth_norm;         /* 0: the beams have peak 1 (default); 1: each
+                                    smoothed value is divided by the L2 norm of
+                                    the kernel on its clipped window             */
+    int32_t switch_area;         /* areas compared by the switch: 0 pi s^2 of
+                                    the fitted Gaussians (default); 1 the
+                                    deconvolved pi (s^2 - omega_b^2)             */
     double window_sigmas;        /* window half-width factor c_w; default 5      */
     double max_width;            /* upper bound on s; 0 = max(omega_b, min(H,W)/8) */
     double lm_mu0;               /* initial damping; default 1e-3                */
@@ -133,6 +144,7 @@ typedef struct {
     int64_t pixels_evaluated;    /* pixel evaluations summed over the LM trials  */
     int64_t gram_flops;          /* (n+1)(n+2) per pixel evaluation: the FP32
                                     multiply-adds of [J r]^T [J r], n = 4 m      */
+    int64_t smoothed;            /* fits started from the smoothing method       */
 } asp_run_report;
 
 /* Fill *opt with the defaults above. */
@@ -252,8 +264,42 @@ asp_status asp_fit_profile(asp_ctx *ctx, double *out, int32_t n);
 /* Give the context a network (host array of n = ASP_MLP_PARAMS floats,
  * copied). */
 asp_status asp_set_mlp(asp_ctx *ctx, const float *weights, int64_t n);
-/* 0: simple initial values; 1: the network (needs asp_set_mlp). */
+/* 0: simple initial values; 1: the network (needs asp_set_mlp); 2: the
+ * smoothing method with the switch (below). */
 asp_status asp_set_init_mode(asp_ctx *ctx, int32_t mode);
+
+/*
+ * The smoothing method of initial values (Sect. 2 step 1; Sect. 3).  The
+ * residual is smoothed with Gaussian beams of the trial widths
+ * sigma_j = omega_b 2^j (j < smooth_scales, sigma_j not above the width bound
+ * of the fit): C_j(p) is the sum over the window of half-width
+ * max(3, ceil(c_w sigma_j)) around pixel p, clipped to the image, of
+ * exp(-|q - p|^2 / (2 sigma_j^2)) R(q).  The peak among the smoothed images
+ * is the largest |C_j(p)| (smooth_norm 0) or |C_j(p)| / sqrt(N_j(p)), N_j(p)
+ * the sum of the squared kernel on the same window (smooth_norm 1); ties go
+ * to the smaller j, then the smaller row-major p.  The new component then
+ * starts at (C/N, x = column of p, y = row of p, s = sigma_j) -- the
+ * least-squares amplitude of that Gaussian -- and the active set is selected
+ * around that start.  In init mode 2 an iteration uses the smoothing method
+ * unless the previous fit's new component had an area below 5 % of the area
+ * of its start (switch_area); then the simple values are used.  The first
+ * iteration smooths.  The smoothed images are kept on the device and
+ * refreshed only where residual updates changed them.
+ *
+ * asp_smooth_peak: the smoothing method's peak on the current residual
+ * (scale j, pixel, |score| as compared in FP32, start values in FP64; any
+ * pointer may be NULL).  Needs no particular phase and leaves the iteration
+ * state alone.  asp_smooth_map: the smoothed image of scale j (C_j, or
+ * C_j / sqrt(N_j) with smooth_norm 1) as H*W floats into a host buffer.
+ * asp_smooth_widths: the trial widths in use (n <= ASP_MAX_SCALES, fewer when
+ * the width bound drops some).  Images with H W smooth_scales >= 2^32 - 1 are
+ * refused (ASP_ERR_INVALID_ARG).
+ */
+#define ASP_MAX_SCALES 8
+asp_status asp_smooth_peak(asp_ctx *ctx, int32_t *scale, int64_t *idx, float *score,
+                           asp_gauss *start);
+asp_status asp_smooth_map(asp_ctx *ctx, int32_t scale, float *out);
+asp_status asp_smooth_widths(asp_ctx *ctx, double *sigma, int32_t cap, int32_t *n);
 
 /*
  * Record a training pair per iteration into caller-owned device buffers:

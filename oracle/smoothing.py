@@ -106,14 +106,13 @@ def _conv_direct(img: np.ndarray, K: np.ndarray) -> np.ndarray:
 
 
 def smoothed(R: np.ndarray, sigma: float, window_sigmas: float = 5.0,
-             method: str = "fft") -> tuple[np.ndarray, np.ndarray]:
+             method: str = "fft", need_norm: bool = True):
     """(C, N): the residual smoothed with the Gaussian of width sigma, and the
-    squared norm of the clipped kernel at every pixel."""
+    squared norm of the clipped kernel at every pixel (None unless need_norm)."""
     R = np.asarray(R, dtype=np.float64)
     K = kernel(sigma, window_sigmas)
-    ones = np.ones_like(R)
     conv = _conv_fft if method == "fft" else _conv_direct
-    return conv(R, K), conv(ones, K * K)
+    return conv(R, K), (conv(np.ones_like(R), K * K) if need_norm else None)
 
 
 NORMS = ("peak", "l2")
@@ -127,7 +126,7 @@ def scores(R: np.ndarray, omega_b: float, n_scales: int, s_max: float,
         raise ValueError(norm)
     out = []
     for s in widths(omega_b, n_scales, s_max):
-        C, N = smoothed(R, s, window_sigmas, method)
+        C, N = smoothed(R, s, window_sigmas, method, need_norm=(norm == "l2"))
         out.append((s, C, N, C if norm == "peak" else C / np.sqrt(N)))
     return out
 
@@ -152,7 +151,8 @@ def best(R: np.ndarray, omega_b: float, n_scales: int, s_max: float,
     j, p = divmod(flat, R.size)
     s, C, N, S = sc[j]
     r, c = divmod(p, R.shape[1])
-    c_, n_ = float(C.ravel()[p]), float(N.ravel()[p])
+    c_ = float(C.ravel()[p])
+    n_ = float(N.ravel()[p]) if N is not None else score_at(R, s, p, window_sigmas)[1]
     return {"scale": j, "idx": p, "sigma": s, "score": float(S.ravel()[p]), "corr": c_,
             "norm2": n_, "start": np.array([c_ / n_, float(c), float(r), s]),
             "maps": sc, "method": method}

@@ -18,6 +18,7 @@ ASP_OK, ASP_STOP_THRESHOLD, ASP_STOP_MAXITER, ASP_LM_NOT_CONVERGED = 0, 1, 2, 3
 ASP_ERR_INVALID_ARG, ASP_ERR_NONFINITE, ASP_ERR_PSF, ASP_ERR_STATE = -1, -2, -3, -4
 ASP_ERR_CAPACITY, ASP_ERR_DEVICE, ASP_ERR_NOMEM = -5, -6, -7
 MAX_ACTIVE = 16
+MAX_SCALES = 8
 
 # Every symbol include/asp.h declares.
 EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destroy",
@@ -29,7 +30,8 @@ EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destro
            "asp_mlp_last_error", "asp_mlp_loss_grad", "asp_mlp_train", "asp_mlp_forward",
            "asp_mlp_weights", "asp_residual_sumsq", "asp_batch_create", "asp_batch_destroy",
            "asp_batch_last_error", "asp_batch_field", "asp_batch_config", "asp_batch_get_config",
-           "asp_batch_run", "asp_batch_autotune"]
+           "asp_batch_run", "asp_batch_autotune", "asp_smooth_peak", "asp_smooth_map",
+           "asp_smooth_widths"]
 
 MLP_PARAMS = 329220
 MLP_IN = 1024
@@ -47,7 +49,8 @@ class Options(ctypes.Structure):
                 ("max_active", ctypes.c_int32), ("lm_max_iter", ctypes.c_int32),
                 ("init_mode", ctypes.c_int32), ("capacity", ctypes.c_int32),
                 ("fit_solo_tiles", ctypes.c_int32), ("fit_min_tiles", ctypes.c_int32),
-                ("fit_group", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("fit_group", ctypes.c_int32), ("smooth_scales", ctypes.c_int32),
+                ("smooth_norm", ctypes.c_int32), ("switch_area", ctypes.c_int32),
                 ("window_sigmas", ctypes.c_double), ("max_width", ctypes.c_double),
                 ("lm_mu0", ctypes.c_double), ("lm_tol", ctypes.c_double),
                 ("psf_lobe_frac", ctypes.c_double), ("stream", ctypes.c_void_p)]
@@ -88,7 +91,7 @@ class RunReport(ctypes.Structure):
                 ("components", ctypes.c_int64), ("lm_trials", ctypes.c_int64),
                 ("not_converged", ctypes.c_int64), ("fallbacks", ctypes.c_int64),
                 ("pixels_updated", ctypes.c_int64), ("pixels_evaluated", ctypes.c_int64),
-                ("gram_flops", ctypes.c_int64)]
+                ("gram_flops", ctypes.c_int64), ("smoothed", ctypes.c_int64)]
 
 
 COMPONENT_DTYPE = np.dtype([("flux", "<f8"), ("amp", "<f8"), ("x", "<f8"), ("y", "<f8"),
@@ -154,6 +157,9 @@ def lib():
         L.asp_batch_run.argtypes = [vp, i64, P(BatchReport)]
         L.asp_batch_autotune.argtypes = [vp, i64, P(i32), P(i32), P(i32)]
         L.asp_fit_profile.argtypes = [vp, vp, ctypes.c_int32]
+        L.asp_smooth_peak.argtypes = [vp, P(i32), P(i64), P(f32), P(Gauss)]
+        L.asp_smooth_map.argtypes = [vp, i32, vp]
+        L.asp_smooth_widths.argtypes = [vp, vp, i32, P(i32)]
         for name in EXPORTS:
             if name not in ("asp_destroy", "asp_last_error", "asp_mlp_destroy",
                             "asp_mlp_last_error", "asp_batch_destroy", "asp_batch_last_error"):
@@ -302,7 +308,7 @@ class Context:
         self._check(lib().asp_fit_profile(self._ctx, out.ctypes.data, len(out)))
         return dict(zip(self.PROFILE_FIELDS, out.tolist()))
 
-    KERNEL_KINDS = ("peak", "fit", "update", "propose")
+    KERNEL_KINDS = ("peak", "fit", "update", "propose", "smooth")
 
     def kernel_timing(self, on: bool):
         """Record HIP events around every launch of run()/step() (clears totals)."""
@@ -310,9 +316,10 @@ class Context:
 
     def kernel_times(self) -> dict:
         """{kind: (total ms, launches)} from the recorded event pairs."""
-        ms = np.zeros(4)
-        n = np.zeros(4, dtype=np.int64)
-        self._check(lib().asp_kernel_times(self._ctx, ms.ctypes.data, n.ctypes.data, 4))
+        k = len(self.KERNEL_KINDS)
+        ms = np.zeros(k)
+        n = np.zeros(k, dtype=np.int64)
+        self._check(lib().asp_kernel_times(self._ctx, ms.ctypes.data, n.ctypes.data, k))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNEL_KINDS)}
 
     # -- learned start values ------------------------------------------------
@@ -322,8 +329,32 @@ class Context:
         self._check(lib().asp_set_mlp(self._ctx, w.ctypes.data, w.size))
 
     def set_init_mode(self, mode: int):
-        """0 simple initial values, 1 the network's proposal."""
+        """0 simple initial values, 1 the network's proposal, 2 the smoothing
+        method with the 5 % switch."""
         self._check(lib().asp_set_init_mode(self._ctx, int(mode)))
+
+    # -- the smoothing method ------------------------------------------------
+    def smooth_peak(self) -> dict:
+        """The smoothing method's peak on the current residual: scale j, pixel,
+        |score| (FP32, as compared) and the start (a, x, y, s)."""
+        j, idx, sc, g = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_float(), Gauss()
+        self._check(lib().asp_smooth_peak(self._ctx, ctypes.byref(j), ctypes.byref(idx),
+                                          ctypes.byref(sc), ctypes.byref(g)))
+        return {"scale": j.value, "idx": idx.value, "score": sc.value,
+                "start": np.array([g.amp, g.x, g.y, g.width])}
+
+    def smooth_map(self, scale: int) -> np.ndarray:
+        """The smoothed residual of trial width `scale` (H x W float32)."""
+        out = np.empty((self.H, self.W), dtype=np.float32)
+        self._check(lib().asp_smooth_map(self._ctx, int(scale), out.ctypes.data))
+        return out
+
+    def smooth_widths(self) -> np.ndarray:
+        out = np.zeros(MAX_SCALES)
+        n = ctypes.c_int32()
+        self._check(lib().asp_smooth_widths(self._ctx, out.ctypes.data, MAX_SCALES,
+                                            ctypes.byref(n)))
+        return out[: n.value]
 
     def record(self, patches, targets, flags):
         """Record a (patch, target, flag) triple per iteration into device tensors

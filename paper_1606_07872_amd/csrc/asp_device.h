@@ -69,6 +69,13 @@ struct DevState {
     unsigned long long prof[kProfSlots];
     // training-sample recording: slots filled
     int64_t rec_n;
+    // the smoothing method: this iteration smooths; smooth_start is current
+    int32_t smooth_now, smooth_ready;
+    int32_t smooth_scale, pad2;    // scale j of the start
+    int64_t smooth_idx;            // its pixel
+    float smooth_score, pad3;      // its |score| as compared
+    double smooth_start[4];        // (a, x, y, s)
+    unsigned long long sum_smoothed;    // fits started from it
 };
 
 // State of one fit shared by the work-groups of the fit kernel.  The
@@ -87,6 +94,26 @@ struct FitGlobal {
     unsigned int gen;                   // publication counter
     unsigned int top;                   // second-level arrivals (one per group)
     unsigned int arrive_g[kMaxGroups];  // first-level arrivals (one per work-group)
+};
+
+// The smoothing method's kernels: trial widths, taps and the device copy of
+// the smoothed images.  Output tiles are kSmTile x kSmTile pixels; a thread
+// computes kSmRb consecutive outputs along the filter axis.
+constexpr int kMaxScales = ASP_MAX_SCALES;
+constexpr int kSmTile = 64;
+constexpr int kSmRb = 16;
+struct SmoothParams {
+    float *vt;                     // n planes W x H: the column pass, transposed
+    const float *taps;             // scale j at off[j]: kSmRb nb[j] taps, zero past 2h
+    const float *wx, *wy;          // scale j at j W (j H): 1 / sqrt(row sum of k^2) (norm 1)
+    unsigned long long *keys;      // n x ntiles: per tile and scale, the packed maximum
+    int32_t *dirty_a, *dirty_b;    // n x ntiles: tile of the column (row) pass is stale
+    float *map;                    // optional H x W output of one scale's smoothed image
+    int32_t map_scale;
+    int32_t n, norm, switch_area;
+    int32_t tiles_x, tiles_y;
+    int32_t h[kMaxScales], nb[kMaxScales], off[kMaxScales];
+    double sig[kMaxScales];
 };
 
 // Read-only launch parameters.
@@ -115,6 +142,9 @@ struct Params {
     float *rec_target;             // rec_cap x 4
     int32_t *rec_flag;             // rec_cap: 1 converged fit from the simple values
     int64_t rec_cap;
+    int32_t smooth;                // the smoothing method and its switch are on
+    int32_t pad_s;
+    SmoothParams sm;
 };
 
 // The proposal network in the layout of the inference kernel: W1 and W2
@@ -198,6 +228,11 @@ hipError_t launch_psf_fit(const float *psf, int64_t Hp, int64_t Wp, double lobe_
                           DevState *st, int32_t *work, hipStream_t s);
 hipError_t launch_check_finite(const float *img, int64_t n, int32_t *flag, hipStream_t s);
 hipError_t launch_components(const Params &p, asp_component *out, hipStream_t s);
+// The smoothing method: refresh of the stale tiles of the smoothed images and
+// the pick of the peak.  force = 0: only when the device state says this
+// iteration smooths; 1: always; 2: always, and every tile of the row pass is
+// recomputed (the column pass keeps to its stale tiles).
+hipError_t launch_smooth(const Params &p, int force, hipStream_t s);
 hipError_t launch_propose(const Params &p, const NetParams &net, int use_net, hipStream_t s);
 hipError_t launch_sumsq(const float *img, int64_t n, double *part, int nblk, double *out,
                         hipStream_t s);

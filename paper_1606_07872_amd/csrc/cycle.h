@@ -140,6 +140,30 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
             ++cnt;
         }
     }
+    if (p.sm.n > 0 && rank == 0) {
+        // tiles of the smoothed images that these windows make stale: per
+        // scale j, rows within h_j of a window for the column pass, rows and
+        // columns within h_j for the row pass
+        const int tx = p.sm.tiles_x, ty = p.sm.tiles_y;
+        const int64_t ntl = (int64_t)tx * ty;
+        for (int i = 0; i < nr; ++i) {
+            for (int j = 0; j < p.sm.n; ++j) {
+                const int h = p.sm.h[j];
+                const int y0 = (rb[i][0] - h) < 0 ? 0 : (rb[i][0] - h) / kSmTile;
+                int y1 = (rb[i][1] + h) / kSmTile;
+                if (y1 > ty - 1) y1 = ty - 1;
+                const int xa0 = rb[i][2] / kSmTile, xa1 = rb[i][3] / kSmTile;
+                const int xb0 = (rb[i][2] - h) < 0 ? 0 : (rb[i][2] - h) / kSmTile;
+                int xb1 = (rb[i][3] + h) / kSmTile;
+                if (xb1 > tx - 1) xb1 = tx - 1;
+                const int ny = y1 - y0 + 1, nxa = xa1 - xa0 + 1, nxb = xb1 - xb0 + 1;
+                for (int q = t; q < ny * nxa; q += blockDim.x)
+                    p.sm.dirty_a[j * ntl + (int64_t)(y0 + q / nxa) * tx + xa0 + q % nxa] = 1;
+                for (int q = t; q < ny * nxb; q += blockDim.x)
+                    p.sm.dirty_b[j * ntl + (int64_t)(y0 + q / nxb) * tx + xb0 + q % nxb] = 1;
+            }
+        }
+    }
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
     if ((t & 63) == 0) cnt_s[t >> 6] = cnt;
     __syncthreads();

@@ -67,11 +67,12 @@ struct WGShared {
     int64_t idx, npx_c;
     // selection scratch
     uint32_t mask[kT];
-    double t0[4];                  // the simple start of the new component
+    double t0[4];                  // the start of the new component (simple or smoothing)
     double alt[4];                 // a proposal start, compared with t0 by the objective
     int32_t alt_pending, chose_prop;
     int32_t hsel;                  // which of the two Gram buffers holds the current point
-    double sel[2];                 // peak pixel (x, y): the active set is selected around it
+    double sel[3];                 // (x, y, s) of the start: the active set is selected around it
+    int32_t use_smooth;            // the start is the smoothing method's
     int32_t nch, sel_done;
     unsigned long long key;        // the peak key of this fit (collect_peak_key)
     // batched fields (leader and followers)
@@ -186,7 +187,7 @@ __device__ inline bool too_close(double xj, double yj, double sj, double xm, dou
 __device__ __forceinline__ void consider(const Params &p, WGShared &S, int64_t j, double omega_b)
 {
     const double xj = p.cx[j], yj = p.cy[j], sj = p.cs[j];
-    if (too_close(xj, yj, sj, S.sel[0], S.sel[1], omega_b, omega_b)) return;
+    if (too_close(xj, yj, sj, S.sel[0], S.sel[1], S.sel[2], omega_b)) return;
     // a proposal start is a second place of the new component
     if (S.alt_pending && too_close(xj, yj, sj, S.alt[1], S.alt[2], S.alt[3], omega_b)) return;
     for (int u = 0; u < S.nch; ++u) {
@@ -209,7 +210,13 @@ __device__ __forceinline__ void setup_fit(const Params &p, FitGlobal *G, WGShare
         const double pv = S.peak;
         double *t0 = S.t0;
         const double cap = width_cap(p);
-        t0[0] = pv; t0[1] = (double)pc; t0[2] = (double)pr; t0[3] = omega_b;
+        if (S.use_smooth) {
+            // the smoothing method's start (Sect. 2 step 1, Sect. 3)
+            const double *q = p.st->smooth_start;
+            t0[0] = q[0]; t0[1] = q[1]; t0[2] = q[2]; t0[3] = q[3];
+        } else {
+            t0[0] = pv; t0[1] = (double)pc; t0[2] = (double)pr; t0[3] = omega_b;
+        }
         S.alt_pending = use_prop ? 1 : 0;
         S.chose_prop = 0;
         if (use_prop) {
@@ -230,17 +237,17 @@ __device__ __forceinline__ void setup_fit(const Params &p, FitGlobal *G, WGShare
             if (!(a[3] >= omega_b)) a[3] = omega_b;
             if (a[3] > cap) a[3] = cap;
         }
-        // candidates: inside the simple start's window (peak pixel, omega_b),
-        // whatever the new component's start
-        S.sel[0] = (double)pc;
-        S.sel[1] = (double)pr;
-        make_window((double)pc, (double)pr, halfwidth(omega_b, p.window_sigmas), p.H, p.W,
-                    S.win[0]);
+        // candidates: inside the start's window (the simple start, peak pixel
+        // and omega_b, also when a proposal competes; or the smoothing start)
+        S.sel[0] = t0[1];
+        S.sel[1] = t0[2];
+        S.sel[2] = t0[3];
+        make_window(t0[1], t0[2], halfwidth(t0[3], p.window_sigmas), p.H, p.W, S.win[0]);
         S.nch = 0;
         S.sel_done = (p.max_active <= 1) ? 1 : 0;
     }
     __syncthreads();
-    const double a0 = S.peak;
+    const double a0 = S.t0[0];
     const int32_t b0 = S.win[0][0], b1 = S.win[0][1], b2 = S.win[0][2], b3 = S.win[0][3];
     const int64_t L = p.st->L;
     constexpr int64_t kSeg = (int64_t)kT * 32;
@@ -982,10 +989,23 @@ __device__ __forceinline__ void commit(const Params &p, WGShared &S)
         st->sum_trials += (unsigned long long)trials;
         st->not_converged += S.converged ? 0ull : 1ull;
         st->fallbacks += (unsigned long long)S.used_fallback;
-        st->init_source = S.use_prop ? st->have_proposal : 0;
+        st->init_source = S.use_prop ? st->have_proposal : (S.use_smooth ? 3 : 0);
         st->start_prop = S.chose_prop && !S.used_fallback;
-        for (int i = 0; i < 4; ++i) st->init[i] = S.use_prop ? st->proposal[i] : 0.0;
+        for (int i = 0; i < 4; ++i)
+            st->init[i] = S.use_prop ? st->proposal[i] : (S.use_smooth ? S.t0[i] : 0.0);
         st->have_proposal = 0;
+        if (p.smooth) {
+            // Sect. 3's switch: the simple values next time when the new
+            // component's fitted area fell below 5 % of its start's area
+            const double s0 = S.t0[3], s1 = S.th_c[3], wb = st->omega_b;
+            const bool shrank = p.sm.switch_area
+                                    ? __dsub_rn(__dmul_rn(s1, s1), __dmul_rn(wb, wb)) <
+                                          __dmul_rn(0.05, __dsub_rn(__dmul_rn(s0, s0), __dmul_rn(wb, wb)))
+                                    : __dmul_rn(s1, s1) < __dmul_rn(0.05, __dmul_rn(s0, s0));
+            st->smooth_now = shrank ? 0 : 1;
+            st->smooth_ready = 0;
+            st->sum_smoothed += S.use_smooth ? 1ull : 0ull;
+        }
         if (p.rec_cap > 0 && st->rec_n < p.rec_cap) {
             // the training pair of this iteration: the patch is already in place
             const int64_t n = st->rec_n;
@@ -1120,6 +1140,7 @@ __device__ __forceinline__ void fit_begin(const Params &p, WGShared &S, bool abo
     S.trials_total = 0;
     S.used_fallback = 0;
     S.use_prop = (p.use_proposal && st->have_proposal) ? 1 : 0;
+    S.use_smooth = (p.smooth && !S.use_prop && st->smooth_now && st->smooth_ready) ? 1 : 0;
     if (S.stop) st->stop = S.stop;
 }
 

@@ -39,12 +39,17 @@ struct asp_ctx {
     bool timing = false;
     std::vector<hipEvent_t> events;       // 2 per launch slot
     std::vector<int> ev_kind;             // kind of each recorded pair
-    double t_ms[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t t_n[4] = {0, 0, 0, 0};
+    double t_ms[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t t_n[5] = {0, 0, 0, 0, 0};
     // the proposal network (input-major layout) and training-sample recording
     float *net = nullptr;
     asp::NetParams netp{};
     double *sumsq = nullptr;              // 1024 partials + the total
+    // the smoothing method's device buffers (allocated on first use)
+    float *sm_vt = nullptr, *sm_taps = nullptr, *sm_w = nullptr, *sm_map = nullptr;
+    unsigned long long *sm_keys = nullptr;
+    int32_t *sm_dirty = nullptr;
+    bool in_batch = false;                // a field of an asp_batch
     std::string err;
 };
 
@@ -84,6 +89,8 @@ void release(asp_ctx *c)
     (void)hipFree(c->st); (void)hipFree(c->work); (void)hipFree(c->comp_out);
     (void)hipFree(c->fg); (void)hipFree(c->partials); (void)hipFree(c->net);
     (void)hipFree(c->sumsq);
+    (void)hipFree(c->sm_vt); (void)hipFree(c->sm_taps); (void)hipFree(c->sm_w);
+    (void)hipFree(c->sm_map); (void)hipFree(c->sm_keys); (void)hipFree(c->sm_dirty);
     if (c->st_host) (void)hipHostFree(c->st_host);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -112,6 +119,121 @@ unsigned long long spin_limit_ticks(int device)
     return (unsigned long long)rate_khz * 2000ull;
 }
 
+// The smoothing method's trial widths, taps and buffers (Sect. 2 step 1,
+// Sect. 3).  Widths omega_b 2^j, j < smooth_scales, not above the fit's width
+// bound; taps k(d) = exp(-(d - h)^2 / (2 sigma^2)), d = 0 .. 2h, rounded to
+// FP32 and padded with zeros to whole blocks of kSmRb.
+asp_status setup_smoothing(asp_ctx *c)
+{
+    if (c->sm_vt) return ASP_OK;
+    const int64_t H = c->H, W = c->W, N = H * W;
+    const double wb = c->st_host->omega_b;
+    double cap = c->opt.max_width > 0.0 ? c->opt.max_width : (double)(H < W ? H : W) / 8.0;
+    if (cap < wb) cap = wb;
+    const int want = c->opt.smooth_scales == 0 ? 5 : c->opt.smooth_scales;
+    asp::SmoothParams &S = c->P.sm;
+    S = asp::SmoothParams{};
+    std::vector<float> taps;
+    int n = 0;
+    for (int j = 0; j < want; ++j) {
+        const double sig = wb * (double)(1 << j);
+        if (j > 0 && sig > cap) break;
+        const int h = asp::halfwidth(sig, c->opt.window_sigmas);
+        const int nb = (2 * h + 1 + asp::kSmRb - 1) / asp::kSmRb;
+        S.sig[n] = sig;
+        S.h[n] = h;
+        S.nb[n] = nb;
+        S.off[n] = (int32_t)taps.size();
+        for (int d = 0; d < nb * asp::kSmRb; ++d) {
+            const double dd = (double)(d - h);
+            taps.push_back(d <= 2 * h ? (float)exp(-(dd * dd) / (2.0 * sig * sig)) : 0.0f);
+        }
+        ++n;
+    }
+    if ((double)N * (double)n >= 4294967295.0)
+        return fail(c, ASP_ERR_INVALID_ARG, "image too large for the smoothing method's keys");
+    // norm factors 1 / sqrt(sum of k^2 over the clipped 1-D window), FP64
+    std::vector<float> w((size_t)n * (W + H));
+    for (int j = 0; j < n; ++j) {
+        const int h = S.h[j];
+        const double sig = S.sig[j];
+        auto f = [&](int64_t pos, int64_t len) {
+            double acc = 0.0;
+            for (int d = -h; d <= h; ++d) {
+                if (pos + d < 0 || pos + d >= len) continue;
+                const double k = exp(-((double)d * d) / (2.0 * sig * sig));
+                acc += k * k;
+            }
+            return (float)(1.0 / sqrt(acc));
+        };
+        for (int64_t x = 0; x < W; ++x) w[(size_t)j * W + x] = f(x, W);
+        for (int64_t y = 0; y < H; ++y) w[(size_t)n * W + (size_t)j * H + y] = f(y, H);
+    }
+    S.n = n;
+    S.norm = c->opt.smooth_norm;
+    S.switch_area = c->opt.switch_area;
+    S.tiles_x = (int32_t)((W + asp::kSmTile - 1) / asp::kSmTile);
+    S.tiles_y = (int32_t)((H + asp::kSmTile - 1) / asp::kSmTile);
+    const int64_t ntiles = (int64_t)S.tiles_x * S.tiles_y;
+    S.map_scale = -1;
+    auto bad = [&](hipError_t e) {
+        (void)hipFree(c->sm_vt); (void)hipFree(c->sm_taps); (void)hipFree(c->sm_w);
+        (void)hipFree(c->sm_keys); (void)hipFree(c->sm_dirty);
+        c->sm_vt = c->sm_taps = c->sm_w = nullptr;
+        c->sm_keys = nullptr;
+        c->sm_dirty = nullptr;
+        S = asp::SmoothParams{};
+        return fail(c, e == hipErrorOutOfMemory ? ASP_ERR_NOMEM : ASP_ERR_DEVICE,
+                    std::string("smoothing buffers: ") + hipGetErrorString(e));
+    };
+    hipError_t e = dev_alloc(&c->sm_vt, (size_t)n * N);
+    if (e == hipSuccess) e = dev_alloc(&c->sm_taps, taps.size());
+    if (e == hipSuccess) e = dev_alloc(&c->sm_w, w.size());
+    if (e == hipSuccess) e = dev_alloc(&c->sm_keys, (size_t)n * ntiles);
+    if (e == hipSuccess) e = dev_alloc(&c->sm_dirty, (size_t)2 * n * ntiles);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->sm_taps, taps.data(), sizeof(float) * taps.size(),
+                           hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->sm_w, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice,
+                           c->stream);
+    // every tile stale (any nonzero byte pattern marks a tile)
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->sm_dirty, 1, sizeof(int32_t) * 2 * n * ntiles, c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->sm_keys, 0, sizeof(unsigned long long) * n * ntiles, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return bad(e);
+    S.vt = c->sm_vt;
+    S.taps = c->sm_taps;
+    S.wx = c->sm_w;
+    S.wy = c->sm_w + (size_t)n * W;
+    S.keys = c->sm_keys;
+    S.dirty_a = c->sm_dirty;
+    S.dirty_b = c->sm_dirty + (size_t)n * ntiles;
+    return ASP_OK;
+}
+
+// Init mode 2: buffers, every tile stale, and the next iteration smooths.
+asp_status enter_smoothing(asp_ctx *c)
+{
+    const bool fresh = c->sm_vt == nullptr;
+    asp_status s = setup_smoothing(c);
+    if (s != ASP_OK) return s;
+    const int64_t ntiles = (int64_t)c->P.sm.tiles_x * c->P.sm.tiles_y;
+    if (!fresh)
+        HIP_OR_FAIL(c, hipMemsetAsync(c->sm_dirty, 1, sizeof(int32_t) * 2 * c->P.sm.n * ntiles,
+                                      c->stream));
+    DevState *h = c->st_host;
+    h->smooth_now = 1;
+    h->smooth_ready = 0;
+    HIP_OR_FAIL(c, hipMemcpyAsync((char *)c->st + offsetof(DevState, smooth_now), &h->smooth_now,
+                                  2 * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->P.smooth = 1;
+    return ASP_OK;
+}
+
 asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t W,
                          const float *psf, bool psf_dev, int64_t Hp, int64_t Wp, float gain,
                          float threshold, const asp_options *opt_in, asp_ctx **out)
@@ -129,7 +251,9 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
         opt = *opt_in;
     }
     if (opt.max_iter < 0 || opt.max_active < 1 || opt.max_active > ASP_MAX_ACTIVE ||
-        opt.lm_max_iter < 1 || opt.init_mode < 0 || opt.init_mode > 1 || opt.capacity < 0 ||
+        opt.lm_max_iter < 1 || opt.init_mode < 0 || opt.init_mode > 2 || opt.capacity < 0 ||
+        opt.smooth_scales < 0 || opt.smooth_scales > ASP_MAX_SCALES || opt.smooth_norm < 0 ||
+        opt.smooth_norm > 1 || opt.switch_area < 0 || opt.switch_area > 1 ||
         opt.fit_solo_tiles < -1 || opt.fit_min_tiles < 0 || opt.fit_group < 0 ||
         !(opt.window_sigmas > 0.0) || !(opt.max_width >= 0.0) || !(opt.lm_mu0 > 0.0) ||
         !(opt.lm_tol > 0.0) || !(opt.psf_lobe_frac > 0.0 && opt.psf_lobe_frac < 1.0))
@@ -246,6 +370,10 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     }
     P.fg = c->fg;
     P.partials = c->partials;
+    if (opt.init_mode == 2) {
+        asp_status s = enter_smoothing(c);
+        if (s != ASP_OK) return bail(s);
+    }
     *out = c;
     return ASP_OK;
 #undef CREATE_HIP
@@ -300,6 +428,8 @@ asp_status enqueue_iteration(asp_ctx *c)
     if (c->opt.init_mode == 1 && !c->net)
         return fail(c, ASP_ERR_STATE, "learned start values need a network (asp_set_mlp)");
     asp_status s = timed(c, 0, [&] { return asp::launch_peak(c->P, c->peak_grid, c->stream); });
+    if (s == ASP_OK && c->P.smooth)
+        s = timed(c, 4, [&] { return asp::launch_smooth(c->P, 0, c->stream); });
     if (s == ASP_OK && (use_net(c) || c->P.rec_cap > 0))
         s = timed(c, 3, [&] {
             return asp::launch_propose(c->P, c->netp, use_net(c) ? 1 : 0, c->stream);
@@ -363,6 +493,7 @@ asp_status asp_find_peak(asp_ctx *c, int64_t *idx, float *value)
     if (!c) return ASP_ERR_INVALID_ARG;
     HIP_OR_FAIL(c, asp::launch_peak(c->P, c->peak_grid, c->stream));
     HIP_OR_FAIL(c, asp::launch_peak_decode(c->P, c->stream));
+    if (c->P.smooth) HIP_OR_FAIL(c, asp::launch_smooth(c->P, 0, c->stream));
     asp_status s = pull_all(c);
     if (s != ASP_OK) return s;
     if (idx) *idx = c->st_host->idx;
@@ -460,7 +591,8 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
     const int64_t k0 = c->st_host->k;
     const unsigned long long t0 = c->st_host->sum_trials, nc0 = c->st_host->not_converged,
                              fb0 = c->st_host->fallbacks, up0 = c->st_host->sum_update_px,
-                             ep0 = c->st_host->sum_eval_px, gf0 = c->st_host->sum_gram_flops;
+                             ep0 = c->st_host->sum_eval_px, gf0 = c->st_host->sum_gram_flops,
+                             sm0 = c->st_host->sum_smoothed;
     int64_t done = 0;
     asp_status result = stop_status(c);
     while (result == ASP_OK && done < n_iter) {
@@ -489,6 +621,7 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
         rep->pixels_updated = (int64_t)(c->st_host->sum_update_px - up0);
         rep->pixels_evaluated = (int64_t)(c->st_host->sum_eval_px - ep0);
         rep->gram_flops = (int64_t)(c->st_host->sum_gram_flops - gf0);
+        rep->smoothed = (int64_t)(c->st_host->sum_smoothed - sm0);
     }
     return result;
 }
@@ -599,13 +732,13 @@ asp_status asp_kernel_timing(asp_ctx *c, int32_t on)
         if (s != ASP_OK) return s;
     }
     c->timing = on != 0;
-    for (int i = 0; i < 4; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
+    for (int i = 0; i < 5; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
     return ASP_OK;
 }
 
 asp_status asp_kernel_times(asp_ctx *c, double *ms, int64_t *launches, int32_t n)
 {
-    if (!c || n < 0 || n > 4 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
+    if (!c || n < 0 || n > 5 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i) { ms[i] = c->t_ms[i]; launches[i] = c->t_n[i]; }
     return ASP_OK;
 }
@@ -634,10 +767,76 @@ asp_status asp_set_mlp(asp_ctx *c, const float *weights, int64_t n)
 
 asp_status asp_set_init_mode(asp_ctx *c, int32_t mode)
 {
-    if (!c || mode < 0 || mode > 1) return ASP_ERR_INVALID_ARG;
+    if (!c || mode < 0 || mode > 2) return ASP_ERR_INVALID_ARG;
     if (mode == 1 && !c->net) return fail(c, ASP_ERR_STATE, "no network set (asp_set_mlp)");
+    if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_set_init_mode inside a step-API sequence");
+    if (mode == 2) {
+        if (c->in_batch)
+            return fail(c, ASP_ERR_STATE, "the smoothing method is not available to batched fields");
+        asp_status s = enter_smoothing(c);
+        if (s != ASP_OK) return s;
+    } else {
+        c->P.smooth = 0;
+    }
     c->opt.init_mode = mode;
     return ASP_OK;
+}
+
+asp_status asp_smooth_peak(asp_ctx *c, int32_t *scale, int64_t *idx, float *score,
+                           asp_gauss *start)
+{
+    if (!c) return ASP_ERR_INVALID_ARG;
+    if (c->in_batch)
+        return fail(c, ASP_ERR_STATE, "the smoothing method is not available to batched fields");
+    asp_status s = setup_smoothing(c);
+    if (s != ASP_OK) return s;
+    HIP_OR_FAIL(c, asp::launch_smooth(c->P, 1, c->stream));
+    s = pull_all(c);
+    if (s != ASP_OK) return s;
+    const DevState *h = c->st_host;
+    if (!h->smooth_ready) return fail(c, ASP_ERR_DEVICE, "the smoothing pick found no maximum");
+    if (scale) *scale = h->smooth_scale;
+    if (idx) *idx = h->smooth_idx;
+    if (score) *score = h->smooth_score;
+    if (start) {
+        start->amp = h->smooth_start[0];
+        start->x = h->smooth_start[1];
+        start->y = h->smooth_start[2];
+        start->width = h->smooth_start[3];
+    }
+    return ASP_OK;
+}
+
+asp_status asp_smooth_map(asp_ctx *c, int32_t scale, float *out)
+{
+    if (!c || !out) return ASP_ERR_INVALID_ARG;
+    if (c->in_batch)
+        return fail(c, ASP_ERR_STATE, "the smoothing method is not available to batched fields");
+    asp_status s = setup_smoothing(c);
+    if (s != ASP_OK) return s;
+    if (scale < 0 || scale >= c->P.sm.n) return fail(c, ASP_ERR_INVALID_ARG, "no such scale");
+    if (!c->sm_map) HIP_OR_FAIL(c, dev_alloc(&c->sm_map, (size_t)(c->H * c->W)));
+    asp::Params P = c->P;
+    P.sm.map = c->sm_map;
+    P.sm.map_scale = scale;
+    HIP_OR_FAIL(c, asp::launch_smooth(P, 2, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(out, c->sm_map, sizeof(float) * c->H * c->W,
+                                  hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return ASP_OK;
+}
+
+asp_status asp_smooth_widths(asp_ctx *c, double *sigma, int32_t cap, int32_t *n)
+{
+    if (!c || cap < 0 || (cap > 0 && !sigma)) return ASP_ERR_INVALID_ARG;
+    if (c->in_batch)
+        return fail(c, ASP_ERR_STATE, "the smoothing method is not available to batched fields");
+    asp_status s = setup_smoothing(c);
+    if (s != ASP_OK) return s;
+    const int m = c->P.sm.n;
+    if (n) *n = m;
+    for (int j = 0; j < m && j < cap; ++j) sigma[j] = c->P.sm.sig[j];
+    return cap < m ? ASP_ERR_CAPACITY : ASP_OK;
 }
 
 asp_status asp_record(asp_ctx *c, float *patches, float *targets, int32_t *flags, int64_t cap)
@@ -800,11 +999,13 @@ asp_status asp_batch_create(int32_t n_fields, const float *const *dirty, const i
         o = *opt;
     }
     o.stream = b->stream;
+    if (o.init_mode == 2) return bail(ASP_ERR_INVALID_ARG);  // no smoothing method in batches
     for (int32_t i = 0; i < n_fields; ++i) {
         asp_ctx *c = nullptr;
         asp_status s = asp_create(dirty[i], H[i], W[i], psf[i], Hp[i], Wp[i], gain[i],
                                   threshold[i], &o, &c);
         if (s != ASP_OK) return bail(s);
+        c->in_batch = true;
         b->ctx.push_back(c);
     }
     b->grid = asp::batch_grid_size(b->device);
