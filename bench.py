@@ -18,6 +18,13 @@ Besides the throughput the line carries:
   cpu_baseline  the FP64 oracle, single-threaded, continuing the same run
                 from the state at the start of the timed region for a bounded
                 number of seconds
+  smoothing     the smoothing method of initial values with the 5 % switch
+                (init mode 2) on the same field: a full refresh of the
+                smoothed images (every tile, both passes, all trial widths)
+                against the FP32 vector peak, and the same iterations as the
+                timed region run in init mode 2 (throughput, the share of
+                fits started from the smoothing method, the incremental
+                refresh per iteration, residual RMS against the plain run)
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -133,6 +140,73 @@ def learned_vs_plain(args, f, wpath, rep, secs, rms_plain, torch, asp):
     return out
 
 
+def smoothing_leg(args, f, rep, secs, rms_plain, torch, asp):
+    """The smoothing method on the same field (see the module docstring)."""
+    d_dirty = torch.from_numpy(f.dirty).cuda()
+    d_psf = torch.from_numpy(f.psf).cuda()
+    total = args.warmup + args.steps
+    ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=max(f.max_iter, total),
+                      max_active=f.max_active, fit_solo_tiles=args.solo_tiles,
+                      fit_min_tiles=args.min_tiles, fit_group=args.group)
+    del d_dirty, d_psf
+    widths = [float(w) for w in ctx.smooth_widths()]
+    # full refreshes: every tile stale (entering init mode 2 marks them), then
+    # one pick, timed with HIP events on the context's stream
+    ctx.kernel_timing(True)
+    reps = 3
+    px0, fl0 = ctx.smooth_work()
+    for _ in range(reps):
+        ctx.set_init_mode(2)
+        ctx.smooth_peak()
+    px1, fl1 = ctx.smooth_work()
+    kt = ctx.kernel_times()
+    ms, n = kt["smooth_passes"]
+    full_s = ms / reps * 1e-3
+    flops = (fl1 - fl0) / reps
+    achieved = flops / full_s / 1e12 if full_s > 0 else 0.0
+    full = {"kernels": "k_smooth_cols + k_smooth_rows", "bound": "alu", "achieved": achieved,
+            "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+            "frac_of_unpacked_fp32": achieved / (PEAK_FP32_VECTOR_TFLOPS / 2),
+            "ms": full_s * 1e3, "flops": flops, "pixels": (px1 - px0) / reps,
+            "pick_us": kt["smooth_pick"][0] / max(kt["smooth_pick"][1], 1) * 1e3}
+    log(f"smoothing full refresh {json.dumps(full)}")
+    # the timed region's iterations in init mode 2, from iteration 0
+    ctx.set_init_mode(2)
+    ctx.kernel_timing(False)
+    ctx.run(args.warmup)
+    ctx.kernel_timing(True)
+    px0, fl0 = ctx.smooth_work()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc, r = ctx.run(args.steps)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t1
+    px1, fl1 = ctx.smooth_work()
+    kt = ctx.kernel_times()
+    done = r["iterations"]
+    pm, pn = kt["smooth_passes"]
+    qm, qn = kt["smooth_pick"]
+    out = {"widths": widths, "norm": "peak-1 beams", "switch": "convolved areas",
+           "full_refresh": full,
+           "run": {"iterations": done, "seconds": t_s,
+                   "iterations_per_s": done / t_s if t_s > 0 else 0.0,
+                   "plain_iterations_per_s": rep["iterations"] / secs if secs > 0 else 0.0,
+                   "smoothed_fits": r["smoothed"],
+                   "smoothed_fraction": r["smoothed"] / max(done, 1),
+                   "trials_per_fit": r["lm_trials"] / max(done, 1),
+                   "plain_trials_per_fit": rep["lm_trials"] / max(rep["iterations"], 1),
+                   "rms": ctx.residual_rms(), "plain_rms": rms_plain,
+                   "passes_us_per_iteration": pm / max(done, 1) * 1e3,
+                   "pick_us_per_smoothed_iteration": qm / max(r["smoothed"], 1) * 1e3,
+                   "refresh_pixels_per_smoothed_iteration": (px1 - px0) / max(r["smoothed"], 1),
+                   "refresh_flops_per_smoothed_iteration": (fl1 - fl0) / max(r["smoothed"], 1),
+                   "fit_ms": kt["fit"][0], "passes_ms": pm, "pick_ms": qm}}
+    log(f"smoothing run {json.dumps(out['run'])}")
+    ctx.close()
+    return out
+
+
 def bench_batch(args):
     """64 independent fields of sizes in {256, 512, 1024, 2048}^2, each with its
     own Gaussian PSF: aggregate iterations/s of one graph-captured persistent
@@ -218,6 +292,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-versus-plain start comparison")
     ap.add_argument("--weights", default=None, help="proposal network weights (.npy)")
+    ap.add_argument("--no-smoothing", action="store_true",
+                    help="skip the smoothing-method (init mode 2) leg")
     ap.add_argument("--probe", type=int, default=5,
                     help="iterations per field of each autotuner probe (batch workload)")
     args = ap.parse_args()
@@ -320,6 +396,10 @@ def main():
     if not args.no_learned and os.path.exists(wpath):
         learned = learned_vs_plain(args, f, wpath, rep, secs, rms_plain, torch, asp)
 
+    smoothing = None
+    if not args.no_smoothing:
+        smoothing = smoothing_leg(args, f, rep, secs, rms_plain, torch, asp)
+
     cpu = None
     if want_cpu:
         log(f"oracle baseline for {args.cpu_seconds:.0f}s from iteration {k0}")
@@ -346,6 +426,7 @@ def main():
         "roofline": roofline,
         "hbm": hbm,
         "learned_vs_plain": learned,
+        "smoothing": smoothing,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

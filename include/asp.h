@@ -300,6 +300,10 @@ asp_status asp_smooth_peak(asp_ctx *ctx, int32_t *scale, int64_t *idx, float *sc
                            asp_gauss *start);
 asp_status asp_smooth_map(asp_ctx *ctx, int32_t scale, float *out);
 asp_status asp_smooth_widths(asp_ctx *ctx, double *sigma, int32_t cap, int32_t *n);
+/* Work of the smoothing passes since the context was created: output pixels
+ * inside the image summed over both passes and all scales, and the
+ * multiply-adds they stand for, 2 (2 h_j + 1) flops per pixel of scale j. */
+asp_status asp_smooth_work(asp_ctx *ctx, int64_t *pixels, double *flops);
 
 /*
  * Record a training pair per iteration into caller-owned device buffers:
@@ -390,12 +394,13 @@ asp_status asp_batch_run(asp_batch *batch, int64_t n_iter, asp_batch_report *rep
 asp_status asp_batch_autotune(asp_batch *batch, int64_t probe_iter, int32_t *team_size,
                               int32_t *solo_tiles, int32_t *min_tiles);
 
-/* Diagnostics: per-kernel device time.  With timing on, asp_run and asp_step
- * record a HIP event pair on the context's stream around every launch they
- * make (which adds two event packets per launch); asp_kernel_times returns the
- * summed milliseconds and launch counts, n <= 4 kinds: 0 peak search, 1 LM
- * fit, 2 residual update, 3 proposal / patch recording.  Switching timing on
- * or off clears the totals. */
+/* Diagnostics: per-kernel device time.  With timing on, asp_run, asp_step
+ * and asp_smooth_peak record a HIP event pair on the context's stream around
+ * every launch they make (which adds two event packets per launch);
+ * asp_kernel_times returns the summed milliseconds and launch counts, n <= 6
+ * kinds: 0 peak search, 1 LM fit, 2 residual update, 3 proposal / patch
+ * recording, 4 the smoothing passes (column and row pass together), 5 the
+ * smoothing pick.  Switching timing on or off clears the totals. */
 asp_status asp_kernel_timing(asp_ctx *ctx, int32_t on);
 asp_status asp_kernel_times(asp_ctx *ctx, double *ms, int64_t *launches, int32_t n);
 

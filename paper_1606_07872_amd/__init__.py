@@ -31,7 +31,7 @@ EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destro
            "asp_mlp_weights", "asp_residual_sumsq", "asp_batch_create", "asp_batch_destroy",
            "asp_batch_last_error", "asp_batch_field", "asp_batch_config", "asp_batch_get_config",
            "asp_batch_run", "asp_batch_autotune", "asp_smooth_peak", "asp_smooth_map",
-           "asp_smooth_widths"]
+           "asp_smooth_widths", "asp_smooth_work"]
 
 MLP_PARAMS = 329220
 MLP_IN = 1024
@@ -160,6 +160,7 @@ def lib():
         L.asp_smooth_peak.argtypes = [vp, P(i32), P(i64), P(f32), P(Gauss)]
         L.asp_smooth_map.argtypes = [vp, i32, vp]
         L.asp_smooth_widths.argtypes = [vp, vp, i32, P(i32)]
+        L.asp_smooth_work.argtypes = [vp, P(i64), P(f64)]
         for name in EXPORTS:
             if name not in ("asp_destroy", "asp_last_error", "asp_mlp_destroy",
                             "asp_mlp_last_error", "asp_batch_destroy", "asp_batch_last_error"):
@@ -308,7 +309,7 @@ class Context:
         self._check(lib().asp_fit_profile(self._ctx, out.ctypes.data, len(out)))
         return dict(zip(self.PROFILE_FIELDS, out.tolist()))
 
-    KERNEL_KINDS = ("peak", "fit", "update", "propose", "smooth")
+    KERNEL_KINDS = ("peak", "fit", "update", "propose", "smooth_passes", "smooth_pick")
 
     def kernel_timing(self, on: bool):
         """Record HIP events around every launch of run()/step() (clears totals)."""
@@ -348,6 +349,12 @@ class Context:
         out = np.empty((self.H, self.W), dtype=np.float32)
         self._check(lib().asp_smooth_map(self._ctx, int(scale), out.ctypes.data))
         return out
+
+    def smooth_work(self):
+        """(pixels, flops) of the smoothing passes since creation."""
+        px, fl = ctypes.c_int64(), ctypes.c_double()
+        self._check(lib().asp_smooth_work(self._ctx, ctypes.byref(px), ctypes.byref(fl)))
+        return px.value, fl.value
 
     def smooth_widths(self) -> np.ndarray:
         out = np.zeros(MAX_SCALES)

@@ -76,6 +76,8 @@ struct DevState {
     float smooth_score, pad3;      // its |score| as compared
     double smooth_start[4];        // (a, x, y, s)
     unsigned long long sum_smoothed;    // fits started from it
+    unsigned long long sm_px[2 * ASP_MAX_SCALES];  // image pixels through the column
+                                                   // (j) and row (8 + j) passes
 };
 
 // State of one fit shared by the work-groups of the fit kernel.  The
@@ -108,6 +110,8 @@ struct SmoothParams {
     const float *wx, *wy;          // scale j at j W (j H): 1 / sqrt(row sum of k^2) (norm 1)
     unsigned long long *keys;      // n x ntiles: per tile and scale, the packed maximum
     int32_t *dirty_a, *dirty_b;    // n x ntiles: tile of the column (row) pass is stale
+    int32_t *list_a, *list_b;      // the stale entries j ntiles + tile, each once
+    unsigned int *count;           // entries in list_a, list_b
     float *map;                    // optional H x W output of one scale's smoothed image
     int32_t map_scale;
     int32_t n, norm, switch_area;
@@ -228,11 +232,14 @@ hipError_t launch_psf_fit(const float *psf, int64_t Hp, int64_t Wp, double lobe_
                           DevState *st, int32_t *work, hipStream_t s);
 hipError_t launch_check_finite(const float *img, int64_t n, int32_t *flag, hipStream_t s);
 hipError_t launch_components(const Params &p, asp_component *out, hipStream_t s);
-// The smoothing method: refresh of the stale tiles of the smoothed images and
-// the pick of the peak.  force = 0: only when the device state says this
-// iteration smooths; 1: always; 2: always, and every tile of the row pass is
-// recomputed (the column pass keeps to its stale tiles).
-hipError_t launch_smooth(const Params &p, int force, hipStream_t s);
+// The smoothing method: refresh of the stale tiles of the smoothed images
+// (both passes) and the pick of the peak.  force = 0: only when the device
+// state says this iteration smooths; 1: always; 2: always, and every tile of
+// the row pass is recomputed (the column pass keeps to its stale tiles).
+hipError_t launch_smooth_passes(const Params &p, int force, hipStream_t s);
+hipError_t launch_smooth_pick(const Params &p, int force, hipStream_t s);
+// Every tile of every scale stale, both passes.
+hipError_t launch_smooth_mark_all(const Params &p, hipStream_t s);
 hipError_t launch_propose(const Params &p, const NetParams &net, int use_net, hipStream_t s);
 hipError_t launch_sumsq(const float *img, int64_t n, double *part, int nblk, double *out,
                         hipStream_t s);

@@ -146,21 +146,27 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
         // columns within h_j for the row pass
         const int tx = p.sm.tiles_x, ty = p.sm.tiles_y;
         const int64_t ntl = (int64_t)tx * ty;
-        for (int i = 0; i < nr; ++i) {
-            for (int j = 0; j < p.sm.n; ++j) {
-                const int h = p.sm.h[j];
-                const int y0 = (rb[i][0] - h) < 0 ? 0 : (rb[i][0] - h) / kSmTile;
-                int y1 = (rb[i][1] + h) / kSmTile;
-                if (y1 > ty - 1) y1 = ty - 1;
-                const int xa0 = rb[i][2] / kSmTile, xa1 = rb[i][3] / kSmTile;
-                const int xb0 = (rb[i][2] - h) < 0 ? 0 : (rb[i][2] - h) / kSmTile;
-                int xb1 = (rb[i][3] + h) / kSmTile;
-                if (xb1 > tx - 1) xb1 = tx - 1;
-                const int ny = y1 - y0 + 1, nxa = xa1 - xa0 + 1, nxb = xb1 - xb0 + 1;
-                for (int q = t; q < ny * nxa; q += blockDim.x)
-                    p.sm.dirty_a[j * ntl + (int64_t)(y0 + q / nxa) * tx + xa0 + q % nxa] = 1;
-                for (int q = t; q < ny * nxb; q += blockDim.x)
-                    p.sm.dirty_b[j * ntl + (int64_t)(y0 + q / nxb) * tx + xb0 + q % nxb] = 1;
+        for (int pair = 0; pair < nr * p.sm.n; ++pair) {
+            const int i = pair / p.sm.n, j = pair % p.sm.n;
+            const int h = p.sm.h[j];
+            const int y0 = (rb[i][0] - h) < 0 ? 0 : (rb[i][0] - h) / kSmTile;
+            int y1 = (rb[i][1] + h) / kSmTile;
+            if (y1 > ty - 1) y1 = ty - 1;
+            const int xa0 = rb[i][2] / kSmTile, xa1 = rb[i][3] / kSmTile;
+            const int xb0 = (rb[i][2] - h) < 0 ? 0 : (rb[i][2] - h) / kSmTile;
+            int xb1 = (rb[i][3] + h) / kSmTile;
+            if (xb1 > tx - 1) xb1 = tx - 1;
+            const int ny = y1 - y0 + 1, nxa = xa1 - xa0 + 1, nxb = xb1 - xb0 + 1;
+            // a tile joins a pass's list when its flag goes from 0 to 1
+            for (int q = t; q < ny * nxa; q += blockDim.x) {
+                const int64_t e = j * ntl + (int64_t)(y0 + q / nxa) * tx + xa0 + q % nxa;
+                if (atomicExch(&p.sm.dirty_a[e], 1) == 0)
+                    p.sm.list_a[atomicAdd(&p.sm.count[0], 1u)] = (int32_t)e;
+            }
+            for (int q = t; q < ny * nxb; q += blockDim.x) {
+                const int64_t e = j * ntl + (int64_t)(y0 + q / nxb) * tx + xb0 + q % nxb;
+                if (atomicExch(&p.sm.dirty_b[e], 1) == 0)
+                    p.sm.list_b[atomicAdd(&p.sm.count[1], 1u)] = (int32_t)e;
             }
         }
     }

@@ -39,8 +39,8 @@ struct asp_ctx {
     bool timing = false;
     std::vector<hipEvent_t> events;       // 2 per launch slot
     std::vector<int> ev_kind;             // kind of each recorded pair
-    double t_ms[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    int64_t t_n[5] = {0, 0, 0, 0, 0};
+    double t_ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t t_n[6] = {0, 0, 0, 0, 0, 0};
     // the proposal network (input-major layout) and training-sample recording
     float *net = nullptr;
     asp::NetParams netp{};
@@ -48,7 +48,8 @@ struct asp_ctx {
     // the smoothing method's device buffers (allocated on first use)
     float *sm_vt = nullptr, *sm_taps = nullptr, *sm_w = nullptr, *sm_map = nullptr;
     unsigned long long *sm_keys = nullptr;
-    int32_t *sm_dirty = nullptr;
+    int32_t *sm_dirty = nullptr, *sm_list = nullptr;
+    unsigned int *sm_count = nullptr;
     bool in_batch = false;                // a field of an asp_batch
     std::string err;
 };
@@ -91,6 +92,7 @@ void release(asp_ctx *c)
     (void)hipFree(c->sumsq);
     (void)hipFree(c->sm_vt); (void)hipFree(c->sm_taps); (void)hipFree(c->sm_w);
     (void)hipFree(c->sm_map); (void)hipFree(c->sm_keys); (void)hipFree(c->sm_dirty);
+    (void)hipFree(c->sm_list); (void)hipFree(c->sm_count);
     if (c->st_host) (void)hipHostFree(c->st_host);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -179,9 +181,11 @@ asp_status setup_smoothing(asp_ctx *c)
     auto bad = [&](hipError_t e) {
         (void)hipFree(c->sm_vt); (void)hipFree(c->sm_taps); (void)hipFree(c->sm_w);
         (void)hipFree(c->sm_keys); (void)hipFree(c->sm_dirty);
+        (void)hipFree(c->sm_list); (void)hipFree(c->sm_count);
         c->sm_vt = c->sm_taps = c->sm_w = nullptr;
         c->sm_keys = nullptr;
-        c->sm_dirty = nullptr;
+        c->sm_dirty = c->sm_list = nullptr;
+        c->sm_count = nullptr;
         S = asp::SmoothParams{};
         return fail(c, e == hipErrorOutOfMemory ? ASP_ERR_NOMEM : ASP_ERR_DEVICE,
                     std::string("smoothing buffers: ") + hipGetErrorString(e));
@@ -191,18 +195,16 @@ asp_status setup_smoothing(asp_ctx *c)
     if (e == hipSuccess) e = dev_alloc(&c->sm_w, w.size());
     if (e == hipSuccess) e = dev_alloc(&c->sm_keys, (size_t)n * ntiles);
     if (e == hipSuccess) e = dev_alloc(&c->sm_dirty, (size_t)2 * n * ntiles);
+    if (e == hipSuccess) e = dev_alloc(&c->sm_list, (size_t)2 * n * ntiles);
+    if (e == hipSuccess) e = dev_alloc(&c->sm_count, 2);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->sm_taps, taps.data(), sizeof(float) * taps.size(),
                            hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->sm_w, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice,
                            c->stream);
-    // every tile stale (any nonzero byte pattern marks a tile)
-    if (e == hipSuccess)
-        e = hipMemsetAsync(c->sm_dirty, 1, sizeof(int32_t) * 2 * n * ntiles, c->stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(c->sm_keys, 0, sizeof(unsigned long long) * n * ntiles, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return bad(e);
     S.vt = c->sm_vt;
     S.taps = c->sm_taps;
@@ -211,6 +213,13 @@ asp_status setup_smoothing(asp_ctx *c)
     S.keys = c->sm_keys;
     S.dirty_a = c->sm_dirty;
     S.dirty_b = c->sm_dirty + (size_t)n * ntiles;
+    S.list_a = c->sm_list;
+    S.list_b = c->sm_list + (size_t)n * ntiles;
+    S.count = c->sm_count;
+    // every tile stale
+    e = asp::launch_smooth_mark_all(c->P, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return bad(e);
     return ASP_OK;
 }
 
@@ -220,10 +229,7 @@ asp_status enter_smoothing(asp_ctx *c)
     const bool fresh = c->sm_vt == nullptr;
     asp_status s = setup_smoothing(c);
     if (s != ASP_OK) return s;
-    const int64_t ntiles = (int64_t)c->P.sm.tiles_x * c->P.sm.tiles_y;
-    if (!fresh)
-        HIP_OR_FAIL(c, hipMemsetAsync(c->sm_dirty, 1, sizeof(int32_t) * 2 * c->P.sm.n * ntiles,
-                                      c->stream));
+    if (!fresh) HIP_OR_FAIL(c, asp::launch_smooth_mark_all(c->P, c->stream));
     DevState *h = c->st_host;
     h->smooth_now = 1;
     h->smooth_ready = 0;
@@ -429,7 +435,9 @@ asp_status enqueue_iteration(asp_ctx *c)
         return fail(c, ASP_ERR_STATE, "learned start values need a network (asp_set_mlp)");
     asp_status s = timed(c, 0, [&] { return asp::launch_peak(c->P, c->peak_grid, c->stream); });
     if (s == ASP_OK && c->P.smooth)
-        s = timed(c, 4, [&] { return asp::launch_smooth(c->P, 0, c->stream); });
+        s = timed(c, 4, [&] { return asp::launch_smooth_passes(c->P, 0, c->stream); });
+    if (s == ASP_OK && c->P.smooth)
+        s = timed(c, 5, [&] { return asp::launch_smooth_pick(c->P, 0, c->stream); });
     if (s == ASP_OK && (use_net(c) || c->P.rec_cap > 0))
         s = timed(c, 3, [&] {
             return asp::launch_propose(c->P, c->netp, use_net(c) ? 1 : 0, c->stream);
@@ -493,7 +501,10 @@ asp_status asp_find_peak(asp_ctx *c, int64_t *idx, float *value)
     if (!c) return ASP_ERR_INVALID_ARG;
     HIP_OR_FAIL(c, asp::launch_peak(c->P, c->peak_grid, c->stream));
     HIP_OR_FAIL(c, asp::launch_peak_decode(c->P, c->stream));
-    if (c->P.smooth) HIP_OR_FAIL(c, asp::launch_smooth(c->P, 0, c->stream));
+    if (c->P.smooth) {
+        HIP_OR_FAIL(c, asp::launch_smooth_passes(c->P, 0, c->stream));
+        HIP_OR_FAIL(c, asp::launch_smooth_pick(c->P, 0, c->stream));
+    }
     asp_status s = pull_all(c);
     if (s != ASP_OK) return s;
     if (idx) *idx = c->st_host->idx;
@@ -732,13 +743,13 @@ asp_status asp_kernel_timing(asp_ctx *c, int32_t on)
         if (s != ASP_OK) return s;
     }
     c->timing = on != 0;
-    for (int i = 0; i < 5; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
+    for (int i = 0; i < 6; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
     return ASP_OK;
 }
 
 asp_status asp_kernel_times(asp_ctx *c, double *ms, int64_t *launches, int32_t n)
 {
-    if (!c || n < 0 || n > 5 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
+    if (!c || n < 0 || n > 6 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i) { ms[i] = c->t_ms[i]; launches[i] = c->t_n[i]; }
     return ASP_OK;
 }
@@ -790,8 +801,10 @@ asp_status asp_smooth_peak(asp_ctx *c, int32_t *scale, int64_t *idx, float *scor
         return fail(c, ASP_ERR_STATE, "the smoothing method is not available to batched fields");
     asp_status s = setup_smoothing(c);
     if (s != ASP_OK) return s;
-    HIP_OR_FAIL(c, asp::launch_smooth(c->P, 1, c->stream));
-    s = pull_all(c);
+    s = timed(c, 4, [&] { return asp::launch_smooth_passes(c->P, 1, c->stream); });
+    if (s == ASP_OK) s = timed(c, 5, [&] { return asp::launch_smooth_pick(c->P, 1, c->stream); });
+    if (s == ASP_OK) s = pull_all(c);
+    if (s == ASP_OK) s = harvest(c);
     if (s != ASP_OK) return s;
     const DevState *h = c->st_host;
     if (!h->smooth_ready) return fail(c, ASP_ERR_DEVICE, "the smoothing pick found no maximum");
@@ -819,10 +832,28 @@ asp_status asp_smooth_map(asp_ctx *c, int32_t scale, float *out)
     asp::Params P = c->P;
     P.sm.map = c->sm_map;
     P.sm.map_scale = scale;
-    HIP_OR_FAIL(c, asp::launch_smooth(P, 2, c->stream));
+    HIP_OR_FAIL(c, asp::launch_smooth_passes(P, 2, c->stream));
+    HIP_OR_FAIL(c, asp::launch_smooth_pick(P, 2, c->stream));
     HIP_OR_FAIL(c, hipMemcpyAsync(out, c->sm_map, sizeof(float) * c->H * c->W,
                                   hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return ASP_OK;
+}
+
+asp_status asp_smooth_work(asp_ctx *c, int64_t *pixels, double *flops)
+{
+    if (!c) return ASP_ERR_INVALID_ARG;
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    int64_t px = 0;
+    double fl = 0.0;
+    for (int j = 0; j < c->P.sm.n; ++j) {
+        const unsigned long long n = c->st_host->sm_px[j] + c->st_host->sm_px[asp::kMaxScales + j];
+        px += (int64_t)n;
+        fl += 2.0 * (double)(2 * c->P.sm.h[j] + 1) * (double)n;
+    }
+    if (pixels) *pixels = px;
+    if (flops) *flops = fl;
     return ASP_OK;
 }
 

@@ -8,7 +8,9 @@
 // row pass reads it with unit stride); the row pass gives C_j and its maxima
 // per 64 x 64 tile and scale.  Only tiles whose inputs a residual update
 // changed are recomputed: the update marks, per scale, the tiles within h_j
-// rows (column pass) or h_j rows and columns (row pass) of its windows.
+// rows (column pass) or h_j rows and columns (row pass) of its windows, and
+// appends each newly stale (scale, tile) to the pass's list; a fixed grid of
+// work-groups walks the lists.
 //
 // Each pass is a register-blocked FIR: a thread owns kSmRb consecutive
 // outputs along the filter axis, the 64 lanes of a wave own 64 neighbouring
@@ -23,6 +25,7 @@ namespace {
 constexpr int kT = 256;
 constexpr int TS = kSmTile;
 constexpr int RB = kSmRb;
+constexpr int kPassGrid = 2048;     // work-groups of a pass: 8 per compute unit
 
 // out[i] = sum_{d < RB nb} k[d] x(i + d), i < RB, accumulated in order of d;
 // x(e) is read for e < RB (nb + 1).
@@ -51,15 +54,6 @@ __device__ __forceinline__ void fir(const float *__restrict__ k, int nb, Load lo
 #pragma unroll
         for (int i = 0; i < RB; ++i) cur[i] = nxt[i];
     }
-}
-
-// Tiles of one scale in XCD-major order: work-group b runs on XCD b % 8 and
-// takes the (b / 8)-th tile of that XCD's contiguous run, so that neighbours
-// along the filter axis share their halos in one L2.
-__device__ inline int xcd_tile(int b, int ntiles)
-{
-    const int per = (ntiles + 7) / 8;
-    return (b % 8) * per + b / 8;
 }
 
 __device__ inline bool stale(const Params &p, int force)
@@ -103,24 +97,30 @@ __device__ __forceinline__ void cols_tile(const Params &p, int j, int bx, int by
     }
 }
 
+// Work-group i takes the entries i, i + G, ... of the column pass's list.
 __global__ __launch_bounds__(kT) void k_smooth_cols(Params p, int force)
 {
     if (!stale(p, force)) return;
-    const int ntiles = p.sm.tiles_x * p.sm.tiles_y;
-    const int j = blockIdx.y;
-    // column-major tile order: consecutive tiles are vertical neighbours
-    const int tile = xcd_tile(blockIdx.x, ntiles);
-    if (tile >= ntiles) return;
-    const int bx = tile / p.sm.tiles_y, by = tile % p.sm.tiles_y;
-    const int id = by * p.sm.tiles_x + bx;
-    int32_t *flag = p.sm.dirty_a + (int64_t)j * ntiles + id;
-    if (*flag == 0) return;
+    const int tx = p.sm.tiles_x, ntiles = tx * p.sm.tiles_y;
+    const unsigned int n = p.sm.count[0];
     __shared__ float tr[TS][TS + 1];
-    const int h = p.sm.h[j], nb = p.sm.nb[j];
-    const int64_t lo = (int64_t)by * TS - h, hi = (int64_t)by * TS + (TS - RB) - h + RB * (nb + 1);
-    if (lo >= 0 && hi <= p.H) cols_tile<false>(p, j, bx, by, tr);
-    else cols_tile<true>(p, j, bx, by, tr);
-    if (threadIdx.x == 0) *flag = 0;
+    for (unsigned int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int e = p.sm.list_a[i];
+        const int j = e / ntiles, tile = e % ntiles;
+        const int by = tile / tx, bx = tile % tx;
+        const int h = p.sm.h[j], nb = p.sm.nb[j];
+        const int64_t lo = (int64_t)by * TS - h;
+        const int64_t hi = (int64_t)by * TS + (TS - RB) - h + RB * (nb + 1);
+        __syncthreads();                   // tr of the previous entry is read
+        if (lo >= 0 && hi <= p.H) cols_tile<false>(p, j, bx, by, tr);
+        else cols_tile<true>(p, j, bx, by, tr);
+        if (threadIdx.x == 0) {
+            p.sm.dirty_a[e] = 0;
+            const int64_t rows = p.H - (int64_t)by * TS < TS ? p.H - (int64_t)by * TS : TS;
+            const int64_t cols = p.W - (int64_t)bx * TS < TS ? p.W - (int64_t)bx * TS : TS;
+            atomicAdd(&p.st->sm_px[j], (unsigned long long)(rows * cols));
+        }
+    }
 }
 
 // Row pass of one (tile, scale): C_j(r, c) = sum_{|d| <= h} k(d) V_j(r, c + d),
@@ -176,34 +176,60 @@ __device__ inline unsigned long long wave_max_key(unsigned long long v)
     return v;
 }
 
+// Work-group i takes the entries i, i + G, ... of the row pass's list (of
+// every (scale, tile) with force 2).  The column pass has finished: its list
+// is emptied here.
 __global__ __launch_bounds__(kT) void k_smooth_rows(Params p, int force)
 {
     if (!stale(p, force)) return;
-    const int ntiles = p.sm.tiles_x * p.sm.tiles_y;
-    const int j = blockIdx.y;
-    // row-major tile order: consecutive tiles are horizontal neighbours
-    const int tile = xcd_tile(blockIdx.x, ntiles);
-    if (tile >= ntiles) return;
-    const int by = tile / p.sm.tiles_x, bx = tile % p.sm.tiles_x;
-    int32_t *flag = p.sm.dirty_b + (int64_t)j * ntiles + tile;
-    if (force < 2 && *flag == 0) return;
-    const int h = p.sm.h[j], nb = p.sm.nb[j];
-    const int64_t lo = (int64_t)bx * TS - h, hi = (int64_t)bx * TS + (TS - RB) - h + RB * (nb + 1);
-    const int64_t rows_hi = (int64_t)by * TS + TS;
-    unsigned long long best = (lo >= 0 && hi <= p.W && rows_hi <= p.H)
-                                  ? rows_tile<false>(p, j, bx, by)
-                                  : rows_tile<true>(p, j, bx, by);
-    best = wave_max_key(best);
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.sm.count[0] = 0;
+    const int tx = p.sm.tiles_x, ntiles = tx * p.sm.tiles_y;
+    const unsigned int n = force == 2 ? (unsigned int)(p.sm.n * ntiles) : p.sm.count[1];
     __shared__ unsigned long long wk[kT / 64];
-    if ((threadIdx.x & 63) == 0) wk[threadIdx.x >> 6] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long m = wk[0];
-        for (int i = 1; i < kT / 64; ++i) m = wk[i] > m ? wk[i] : m;
-        p.sm.keys[(int64_t)j * ntiles + tile] = m;
-        *flag = 0;
+    for (unsigned int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int e = force == 2 ? (int)i : p.sm.list_b[i];
+        const int j = e / ntiles, tile = e % ntiles;
+        const int by = tile / tx, bx = tile % tx;
+        const int h = p.sm.h[j], nb = p.sm.nb[j];
+        const int64_t lo = (int64_t)bx * TS - h;
+        const int64_t hi = (int64_t)bx * TS + (TS - RB) - h + RB * (nb + 1);
+        const int64_t rows_hi = (int64_t)by * TS + TS;
+        unsigned long long best = (lo >= 0 && hi <= p.W && rows_hi <= p.H)
+                                      ? rows_tile<false>(p, j, bx, by)
+                                      : rows_tile<true>(p, j, bx, by);
+        best = wave_max_key(best);
+        __syncthreads();                   // wk of the previous entry is read
+        if ((threadIdx.x & 63) == 0) wk[threadIdx.x >> 6] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long m = wk[0];
+            for (int k = 1; k < kT / 64; ++k) m = wk[k] > m ? wk[k] : m;
+            p.sm.keys[e] = m;
+            p.sm.dirty_b[e] = 0;
+            const int64_t rows = p.H - (int64_t)by * TS < TS ? p.H - (int64_t)by * TS : TS;
+            const int64_t cols = p.W - (int64_t)bx * TS < TS ? p.W - (int64_t)bx * TS : TS;
+            atomicAdd(&p.st->sm_px[kMaxScales + j], (unsigned long long)(rows * cols));
+        }
     }
 }
+
+__global__ __launch_bounds__(kT) void k_smooth_mark_all(Params p)
+{
+    const int64_t n = (int64_t)p.sm.n * p.sm.tiles_x * p.sm.tiles_y;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+        p.sm.dirty_a[i] = 1;
+        p.sm.dirty_b[i] = 1;
+        p.sm.list_a[i] = (int32_t)i;
+        p.sm.list_b[i] = (int32_t)i;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p.sm.count[0] = (unsigned int)n;
+        p.sm.count[1] = (unsigned int)n;
+    }
+}
+
+constexpr int kPickT = 1024;        // threads of the pick: 16 waves
+constexpr int kPickChunk = 2048;    // window rows (columns) per LDS table
 
 __device__ inline double block_sum(double v, double *red)
 {
@@ -212,32 +238,34 @@ __device__ inline double block_sum(double v, double *red)
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
-    for (int i = 0; i < kT / 64; ++i) s += red[i];
+    for (int i = 0; i < kPickT / 64; ++i) s += red[i];
     return s;
 }
 
 // The peak over the tile maxima, and the start values in FP64: the
-// least-squares amplitude C / N of that scale's Gaussian on its window.
-__global__ __launch_bounds__(kT) void k_smooth_pick(Params p, int force)
+// least-squares amplitude C / N of that scale's Gaussian on its window.  The
+// window's row and column factors exp(-d^2 / (2 sigma^2)) go to LDS; wave w
+// sums rows w, w + 16, ..., its lanes 64 consecutive columns at a time.
+__global__ __launch_bounds__(kPickT) void k_smooth_pick(Params p, int force)
 {
     if (!stale(p, force)) return;
     DevState *st = p.st;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) p.sm.count[1] = 0;        // the row pass has finished its list
     const int64_t nk = (int64_t)p.sm.n * p.sm.tiles_x * p.sm.tiles_y;
     unsigned long long best = 0;
-    for (int64_t i = t; i < nk; i += kT) {
+    for (int64_t i = t; i < nk; i += kPickT) {
         const unsigned long long k = p.sm.keys[i];
         best = k > best ? k : best;
     }
     best = wave_max_key(best);
-    __shared__ unsigned long long wk[kT / 64];
-    __shared__ double red[kT / 64];
-    constexpr int kChunk = 1024;
-    __shared__ double ey[kChunk];
-    if ((t & 63) == 0) wk[t >> 6] = best;
+    __shared__ unsigned long long wk[kPickT / 64];
+    __shared__ double red[kPickT / 64];
+    __shared__ double ex[kPickChunk], ey[kPickChunk];
+    if (lane == 0) wk[w] = best;
     __syncthreads();
     best = wk[0];
-    for (int i = 1; i < kT / 64; ++i) best = wk[i] > best ? wk[i] : best;
+    for (int i = 1; i < kPickT / 64; ++i) best = wk[i] > best ? wk[i] : best;
     const int64_t H = p.H, W = p.W, N = H * W;
     const uint32_t q = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
     const int j = (int)(q / (uint64_t)N);
@@ -252,24 +280,31 @@ __global__ __launch_bounds__(kT) void k_smooth_pick(Params p, int force)
     const int64_t h = p.sm.h[j];
     const int64_t r0 = r - h > 0 ? r - h : 0, r1 = r + h < H - 1 ? r + h : H - 1;
     const int64_t c0 = c - h > 0 ? c - h : 0, c1 = c + h < W - 1 ? c + h : W - 1;
-    // the window in chunks of kChunk rows; the row factors of a chunk in LDS,
-    // thread t takes columns c0 + t, c0 + t + 256, ...
     double cs = 0.0, ns = 0.0;
-    for (int64_t rb = r0; rb <= r1; rb += kChunk) {
-        const int64_t re = rb + kChunk - 1 < r1 ? rb + kChunk - 1 : r1;
-        __syncthreads();
-        for (int64_t d = t; d <= re - rb; d += kT) {
-            const double dd = (double)(rb + d - r);
-            ey[d] = exp(-(dd * dd) * inv);
-        }
-        __syncthreads();
-        for (int64_t cc = c0 + t; cc <= c1; cc += kT) {
-            const double dx = (double)(cc - c);
-            const double ex = exp(-(dx * dx) * inv);
-            for (int64_t rr = rb; rr <= re; ++rr) {
-                const double kv = ex * ey[rr - rb];
-                cs += kv * (double)p.R[rr * W + cc];
-                ns += kv * kv;
+    for (int64_t rb = r0; rb <= r1; rb += kPickChunk) {
+        const int64_t re = rb + kPickChunk - 1 < r1 ? rb + kPickChunk - 1 : r1;
+        for (int64_t cb = c0; cb <= c1; cb += kPickChunk) {
+            const int64_t ce = cb + kPickChunk - 1 < c1 ? cb + kPickChunk - 1 : c1;
+            __syncthreads();
+            for (int64_t d = t; d <= re - rb; d += kPickT) {
+                const double dd = (double)(rb + d - r);
+                ey[d] = exp(-(dd * dd) * inv);
+            }
+            for (int64_t d = t; d <= ce - cb; d += kPickT) {
+                const double dd = (double)(cb + d - c);
+                ex[d] = exp(-(dd * dd) * inv);
+            }
+            __syncthreads();
+            const int nr = (int)(re - rb + 1), nc = (int)(ce - cb + 1);
+            for (int rr = w; rr < nr; rr += kPickT / 64) {
+                const double fy = ey[rr];
+                const float *row = p.R + (rb + rr) * W + cb;
+#pragma unroll 4
+                for (int cc = lane; cc < nc; cc += 64) {
+                    const double kv = ex[cc] * fy;
+                    cs += kv * (double)row[cc];
+                    ns += kv * kv;
+                }
             }
         }
     }
@@ -289,17 +324,26 @@ __global__ __launch_bounds__(kT) void k_smooth_pick(Params p, int force)
 
 }  // namespace
 
-hipError_t launch_smooth(const Params &p, int force, hipStream_t s)
+hipError_t launch_smooth_passes(const Params &p, int force, hipStream_t s)
 {
-    const int ntiles = p.sm.tiles_x * p.sm.tiles_y;
-    const dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)), (unsigned)p.sm.n);
-    hipLaunchKernelGGL(k_smooth_cols, grid, dim3(kT), 0, s, p, force);
+    const int64_t entries = (int64_t)p.sm.n * p.sm.tiles_x * p.sm.tiles_y;
+    const unsigned grid = (unsigned)(entries < kPassGrid ? entries : kPassGrid);
+    hipLaunchKernelGGL(k_smooth_cols, dim3(grid), dim3(kT), 0, s, p, force);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_smooth_rows, grid, dim3(kT), 0, s, p, force);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_smooth_pick, dim3(1), dim3(kT), 0, s, p, force);
+    hipLaunchKernelGGL(k_smooth_rows, dim3(grid), dim3(kT), 0, s, p, force);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_mark_all(const Params &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_smooth_mark_all, dim3(256), dim3(kT), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_pick(const Params &p, int force, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_smooth_pick, dim3(1), dim3(kPickT), 0, s, p, force);
     return hipGetLastError();
 }
 
