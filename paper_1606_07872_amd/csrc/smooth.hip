@@ -25,7 +25,7 @@ namespace {
 constexpr int kT = 256;
 constexpr int TS = kSmTile;
 constexpr int RB = kSmRb;
-constexpr int kPassGrid = 2048;     // work-groups of a pass: 8 per compute unit
+constexpr int kPassGrid = 2048;     // work-groups of a pass: 8 per compute unit (a multiple of 8)
 
 // out[i] = sum_{d < RB nb} k[d] x(i + d), i < RB, accumulated in order of d;
 // x(e) is read for e < RB (nb + 1).
@@ -54,6 +54,21 @@ __device__ __forceinline__ void fir(const float *__restrict__ k, int nb, Load lo
 #pragma unroll
         for (int i = 0; i < RB; ++i) cur[i] = nxt[i];
     }
+}
+
+// Entries of a list in XCD-contiguous chunks: work-group b runs on XCD b % 8
+// and takes the entries lo + b / 8, lo + b / 8 + G / 8, ... of that XCD's
+// eighth of the list, so that neighbouring tiles (consecutive entries), whose
+// halos overlap, are read through one L2.
+struct Chunk {
+    unsigned int i, hi, step;
+};
+
+__device__ inline Chunk xcd_chunk(unsigned int n)
+{
+    const unsigned int per = (n + 7) / 8, x = blockIdx.x % 8;
+    const unsigned int lo = x * per;
+    return {lo + blockIdx.x / 8, lo + per < n ? lo + per : n, gridDim.x / 8};
 }
 
 __device__ inline bool stale(const Params &p, int force)
@@ -97,14 +112,14 @@ __device__ __forceinline__ void cols_tile(const Params &p, int j, int bx, int by
     }
 }
 
-// Work-group i takes the entries i, i + G, ... of the column pass's list.
+// The column pass over its list of stale (scale, tile) entries.
 __global__ __launch_bounds__(kT) void k_smooth_cols(Params p, int force)
 {
     if (!stale(p, force)) return;
     const int tx = p.sm.tiles_x, ntiles = tx * p.sm.tiles_y;
-    const unsigned int n = p.sm.count[0];
+    const Chunk ch = xcd_chunk(p.sm.count[0]);
     __shared__ float tr[TS][TS + 1];
-    for (unsigned int i = blockIdx.x; i < n; i += gridDim.x) {
+    for (unsigned int i = ch.i; i < ch.hi; i += ch.step) {
         const int e = p.sm.list_a[i];
         const int j = e / ntiles, tile = e % ntiles;
         const int by = tile / tx, bx = tile % tx;
@@ -176,17 +191,16 @@ __device__ inline unsigned long long wave_max_key(unsigned long long v)
     return v;
 }
 
-// Work-group i takes the entries i, i + G, ... of the row pass's list (of
-// every (scale, tile) with force 2).  The column pass has finished: its list
-// is emptied here.
+// The row pass over its list of stale (scale, tile) entries (every entry with
+// force 2).  The column pass has finished: its list is emptied here.
 __global__ __launch_bounds__(kT) void k_smooth_rows(Params p, int force)
 {
     if (!stale(p, force)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) p.sm.count[0] = 0;
     const int tx = p.sm.tiles_x, ntiles = tx * p.sm.tiles_y;
-    const unsigned int n = force == 2 ? (unsigned int)(p.sm.n * ntiles) : p.sm.count[1];
+    const Chunk ch = xcd_chunk(force == 2 ? (unsigned int)(p.sm.n * ntiles) : p.sm.count[1]);
     __shared__ unsigned long long wk[kT / 64];
-    for (unsigned int i = blockIdx.x; i < n; i += gridDim.x) {
+    for (unsigned int i = ch.i; i < ch.hi; i += ch.step) {
         const int e = force == 2 ? (int)i : p.sm.list_b[i];
         const int j = e / ntiles, tile = e % ntiles;
         const int by = tile / tx, bx = tile % tx;
@@ -213,14 +227,19 @@ __global__ __launch_bounds__(kT) void k_smooth_rows(Params p, int force)
     }
 }
 
+// Every entry stale.  The lists hold the tiles in row-major order with the
+// scales of a tile side by side, so that an XCD's chunk is a band of tiles
+// with all their scales (the cost of a tile grows with its scale).
 __global__ __launch_bounds__(kT) void k_smooth_mark_all(Params p)
 {
-    const int64_t n = (int64_t)p.sm.n * p.sm.tiles_x * p.sm.tiles_y;
+    const int64_t ntiles = (int64_t)p.sm.tiles_x * p.sm.tiles_y;
+    const int64_t n = (int64_t)p.sm.n * ntiles;
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
         p.sm.dirty_a[i] = 1;
         p.sm.dirty_b[i] = 1;
-        p.sm.list_a[i] = (int32_t)i;
-        p.sm.list_b[i] = (int32_t)i;
+        const int32_t e = (int32_t)((i % p.sm.n) * ntiles + i / p.sm.n);
+        p.sm.list_a[i] = e;
+        p.sm.list_b[i] = e;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         p.sm.count[0] = (unsigned int)n;
@@ -327,7 +346,8 @@ __global__ __launch_bounds__(kPickT) void k_smooth_pick(Params p, int force)
 hipError_t launch_smooth_passes(const Params &p, int force, hipStream_t s)
 {
     const int64_t entries = (int64_t)p.sm.n * p.sm.tiles_x * p.sm.tiles_y;
-    const unsigned grid = (unsigned)(entries < kPassGrid ? entries : kPassGrid);
+    const int64_t g = entries < kPassGrid ? entries : kPassGrid;
+    const unsigned grid = (unsigned)(8 * ((g + 7) / 8));      // a multiple of the 8 XCDs
     hipLaunchKernelGGL(k_smooth_cols, dim3(grid), dim3(kT), 0, s, p, force);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
