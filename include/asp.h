@@ -125,6 +125,12 @@ typedef struct {
     int32_t switch_area;         /* areas compared by the switch: 0 pi s^2 of
                                     the fitted Gaussians (default); 1 the
                                     deconvolved pi (s^2 - omega_b^2)             */
+    int32_t peak_tiles;          /* 0: the peak search scans the whole residual
+                                    every iteration (default); 1: it keeps the
+                                    maximum of |R| of every 64 x 64 tile on the
+                                    device and rescans only the tiles that the
+                                    residual updates touched (same result)      */
+    int32_t pad0;
     double window_sigmas;        /* window half-width factor c_w; default 5      */
     double max_width;            /* upper bound on s; 0 = max(omega_b, min(H,W)/8) */
     double lm_mu0;               /* initial damping; default 1e-3                */
@@ -145,6 +151,8 @@ typedef struct {
     int64_t gram_flops;          /* (n+1)(n+2) per pixel evaluation: the FP32
                                     multiply-adds of [J r]^T [J r], n = 4 m      */
     int64_t smoothed;            /* fits started from the smoothing method       */
+    int64_t peak_tiles_scanned;  /* 64 x 64 tiles rescanned by the incremental
+                                    peak search (peak_tiles = 1)                 */
 } asp_run_report;
 
 /* Fill *opt with the defaults above. */

@@ -51,6 +51,7 @@ class Options(ctypes.Structure):
                 ("fit_solo_tiles", ctypes.c_int32), ("fit_min_tiles", ctypes.c_int32),
                 ("fit_group", ctypes.c_int32), ("smooth_scales", ctypes.c_int32),
                 ("smooth_norm", ctypes.c_int32), ("switch_area", ctypes.c_int32),
+                ("peak_tiles", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("window_sigmas", ctypes.c_double), ("max_width", ctypes.c_double),
                 ("lm_mu0", ctypes.c_double), ("lm_tol", ctypes.c_double),
                 ("psf_lobe_frac", ctypes.c_double), ("stream", ctypes.c_void_p)]
@@ -91,7 +92,8 @@ class RunReport(ctypes.Structure):
                 ("components", ctypes.c_int64), ("lm_trials", ctypes.c_int64),
                 ("not_converged", ctypes.c_int64), ("fallbacks", ctypes.c_int64),
                 ("pixels_updated", ctypes.c_int64), ("pixels_evaluated", ctypes.c_int64),
-                ("gram_flops", ctypes.c_int64), ("smoothed", ctypes.c_int64)]
+                ("gram_flops", ctypes.c_int64), ("smoothed", ctypes.c_int64),
+                ("peak_tiles_scanned", ctypes.c_int64)]
 
 
 COMPONENT_DTYPE = np.dtype([("flux", "<f8"), ("amp", "<f8"), ("x", "<f8"), ("y", "<f8"),

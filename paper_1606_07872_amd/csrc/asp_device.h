@@ -28,6 +28,19 @@ constexpr int kProfSlots = 12;
 
 constexpr int kPeakSlots = 64;   // wave-size: one slot per lane of the collecting wave
 
+// The incremental peak search: the packed peak key of every kPkTile x kPkTile
+// tile of R, and the list of tiles that residual updates touched since the
+// last search.  tiles_x = 0: the peak search scans the whole image.  It lives
+// in the device state, not in the launch parameters.
+constexpr int kPkTile = 64;
+struct PeakTiles {
+    unsigned long long *keys;      // per tile: (|v| bits << 32) | (0xFFFFFFFF - idx)
+    int32_t *dirty, *list;         // per tile: stale flag; the stale tiles, each once
+    unsigned int *count;           // entries in list
+    int32_t tiles_x, tiles_y;
+};
+
+
 // Mutable per-context state in device memory.
 struct DevState {
     // packed keys (|v| bits << 32) | (0xFFFFFFFF - idx), one slot per
@@ -78,6 +91,8 @@ struct DevState {
     unsigned long long sum_smoothed;    // fits started from it
     unsigned long long sm_px[2 * ASP_MAX_SCALES];  // image pixels through the column
                                                    // (j) and row (8 + j) passes
+    unsigned long long pk_tiles_done;   // tiles rescanned by the incremental peak search
+    PeakTiles pk;                       // the incremental peak search's buffers
 };
 
 // State of one fit shared by the work-groups of the fit kernel.  The
@@ -240,6 +255,10 @@ hipError_t launch_smooth_passes(const Params &p, int force, hipStream_t s);
 hipError_t launch_smooth_pick(const Params &p, int force, hipStream_t s);
 // Every tile of every scale stale, both passes.
 hipError_t launch_smooth_mark_all(const Params &p, hipStream_t s);
+// The incremental peak search: rescan the stale tiles, then reduce the tile
+// keys into the peak key; and every tile stale.
+hipError_t launch_peak_tiles(const Params &p, int ntiles, hipStream_t s);
+hipError_t launch_peak_mark_all(const Params &p, hipStream_t s);
 hipError_t launch_propose(const Params &p, const NetParams &net, int use_net, hipStream_t s);
 hipError_t launch_sumsq(const float *img, int64_t n, double *part, int nblk, double *out,
                         hipStream_t s);

@@ -170,6 +170,21 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
             }
         }
     }
+    if (st->pk.tiles_x > 0 && rank == 0) {
+        // tiles of R that these windows touch, for the incremental peak search
+        const PeakTiles K = st->pk;
+        const int tx = K.tiles_x;
+        for (int i = 0; i < nr; ++i) {
+            const int y0 = rb[i][0] / kPkTile, y1 = rb[i][1] / kPkTile;
+            const int x0 = rb[i][2] / kPkTile, x1 = rb[i][3] / kPkTile;
+            const int nx = x1 - x0 + 1;
+            for (int q = t; q < (y1 - y0 + 1) * nx; q += blockDim.x) {
+                const int e = (y0 + q / nx) * tx + x0 + q % nx;
+                if (atomicExch(&K.dirty[e], 1) == 0)
+                    K.list[atomicAdd(K.count, 1u)] = e;
+            }
+        }
+    }
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
     if ((t & 63) == 0) cnt_s[t >> 6] = cnt;
     __syncthreads();

@@ -50,6 +50,11 @@ struct asp_ctx {
     unsigned long long *sm_keys = nullptr;
     int32_t *sm_dirty = nullptr, *sm_list = nullptr;
     unsigned int *sm_count = nullptr;
+    // the incremental peak search's tile keys, flags and list
+    unsigned long long *pk_keys = nullptr;
+    int32_t *pk_dirty = nullptr;
+    unsigned int *pk_count = nullptr;
+    int pk_tiles = 0;                     // > 0: the incremental peak search is on
     bool in_batch = false;                // a field of an asp_batch
     std::string err;
 };
@@ -93,6 +98,7 @@ void release(asp_ctx *c)
     (void)hipFree(c->sm_vt); (void)hipFree(c->sm_taps); (void)hipFree(c->sm_w);
     (void)hipFree(c->sm_map); (void)hipFree(c->sm_keys); (void)hipFree(c->sm_dirty);
     (void)hipFree(c->sm_list); (void)hipFree(c->sm_count);
+    (void)hipFree(c->pk_keys); (void)hipFree(c->pk_dirty); (void)hipFree(c->pk_count);
     if (c->st_host) (void)hipHostFree(c->st_host);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -259,7 +265,8 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     if (opt.max_iter < 0 || opt.max_active < 1 || opt.max_active > ASP_MAX_ACTIVE ||
         opt.lm_max_iter < 1 || opt.init_mode < 0 || opt.init_mode > 2 || opt.capacity < 0 ||
         opt.smooth_scales < 0 || opt.smooth_scales > ASP_MAX_SCALES || opt.smooth_norm < 0 ||
-        opt.smooth_norm > 1 || opt.switch_area < 0 || opt.switch_area > 1 ||
+        opt.smooth_norm > 1 || opt.switch_area < 0 || opt.switch_area > 1 || opt.peak_tiles < 0 ||
+        opt.peak_tiles > 1 ||
         opt.fit_solo_tiles < -1 || opt.fit_min_tiles < 0 || opt.fit_group < 0 ||
         !(opt.window_sigmas > 0.0) || !(opt.max_width >= 0.0) || !(opt.lm_mu0 > 0.0) ||
         !(opt.lm_tol > 0.0) || !(opt.psf_lobe_frac > 0.0 && opt.psf_lobe_frac < 1.0))
@@ -380,6 +387,26 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
         asp_status s = enter_smoothing(c);
         if (s != ASP_OK) return bail(s);
     }
+    if (opt.peak_tiles) {
+        // the buffers live in the device state; every tile stale: the first
+        // search scans the whole image
+        asp::PeakTiles &K = c->st_host->pk;
+        K.tiles_x = (int32_t)((W + asp::kPkTile - 1) / asp::kPkTile);
+        K.tiles_y = (int32_t)((H + asp::kPkTile - 1) / asp::kPkTile);
+        const size_t nt = (size_t)K.tiles_x * K.tiles_y;
+        CREATE_HIP(dev_alloc(&c->pk_keys, nt));
+        CREATE_HIP(dev_alloc(&c->pk_dirty, 2 * nt));
+        CREATE_HIP(dev_alloc(&c->pk_count, 1));
+        K.keys = c->pk_keys;
+        K.dirty = c->pk_dirty;
+        K.list = c->pk_dirty + nt;
+        K.count = c->pk_count;
+        CREATE_HIP(hipMemcpyAsync((char *)c->st + offsetof(DevState, pk), &K, sizeof(K),
+                                  hipMemcpyHostToDevice, c->stream));
+        CREATE_HIP(asp::launch_peak_mark_all(P, c->stream));
+        CREATE_HIP(hipStreamSynchronize(c->stream));
+        c->pk_tiles = (int)nt;
+    }
     *out = c;
     return ASP_OK;
 #undef CREATE_HIP
@@ -433,7 +460,10 @@ asp_status enqueue_iteration(asp_ctx *c)
 {
     if (c->opt.init_mode == 1 && !c->net)
         return fail(c, ASP_ERR_STATE, "learned start values need a network (asp_set_mlp)");
-    asp_status s = timed(c, 0, [&] { return asp::launch_peak(c->P, c->peak_grid, c->stream); });
+    asp_status s = timed(c, 0, [&] {
+        return c->pk_tiles ? asp::launch_peak_tiles(c->P, c->pk_tiles, c->stream)
+                           : asp::launch_peak(c->P, c->peak_grid, c->stream);
+    });
     if (s == ASP_OK && c->P.smooth)
         s = timed(c, 4, [&] { return asp::launch_smooth_passes(c->P, 0, c->stream); });
     if (s == ASP_OK && c->P.smooth)
@@ -499,7 +529,8 @@ const char *asp_last_error(const asp_ctx *ctx)
 asp_status asp_find_peak(asp_ctx *c, int64_t *idx, float *value)
 {
     if (!c) return ASP_ERR_INVALID_ARG;
-    HIP_OR_FAIL(c, asp::launch_peak(c->P, c->peak_grid, c->stream));
+    if (c->pk_tiles) HIP_OR_FAIL(c, asp::launch_peak_tiles(c->P, c->pk_tiles, c->stream));
+    else HIP_OR_FAIL(c, asp::launch_peak(c->P, c->peak_grid, c->stream));
     HIP_OR_FAIL(c, asp::launch_peak_decode(c->P, c->stream));
     if (c->P.smooth) {
         HIP_OR_FAIL(c, asp::launch_smooth_passes(c->P, 0, c->stream));
@@ -603,7 +634,7 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
     const unsigned long long t0 = c->st_host->sum_trials, nc0 = c->st_host->not_converged,
                              fb0 = c->st_host->fallbacks, up0 = c->st_host->sum_update_px,
                              ep0 = c->st_host->sum_eval_px, gf0 = c->st_host->sum_gram_flops,
-                             sm0 = c->st_host->sum_smoothed;
+                             sm0 = c->st_host->sum_smoothed, pk0 = c->st_host->pk_tiles_done;
     int64_t done = 0;
     asp_status result = stop_status(c);
     while (result == ASP_OK && done < n_iter) {
@@ -633,6 +664,7 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
         rep->pixels_evaluated = (int64_t)(c->st_host->sum_eval_px - ep0);
         rep->gram_flops = (int64_t)(c->st_host->sum_gram_flops - gf0);
         rep->smoothed = (int64_t)(c->st_host->sum_smoothed - sm0);
+        rep->peak_tiles_scanned = (int64_t)(c->st_host->pk_tiles_done - pk0);
     }
     return result;
 }
@@ -1030,7 +1062,8 @@ asp_status asp_batch_create(int32_t n_fields, const float *const *dirty, const i
         o = *opt;
     }
     o.stream = b->stream;
-    if (o.init_mode == 2) return bail(ASP_ERR_INVALID_ARG);  // no smoothing method in batches
+    // the batched kernel has its own peak scan and no smoothing method
+    if (o.init_mode == 2 || o.peak_tiles) return bail(ASP_ERR_INVALID_ARG);
     for (int32_t i = 0; i < n_fields; ++i) {
         asp_ctx *c = nullptr;
         asp_status s = asp_create(dirty[i], H[i], W[i], psf[i], Hp[i], Wp[i], gain[i],
