@@ -25,6 +25,11 @@ Besides the throughput the line carries:
                 timed region run in init mode 2 (throughput, the share of
                 fits started from the smoothing method, the incremental
                 refresh per iteration, residual RMS against the plain run)
+  peak_tiles    the same iterations with the incremental peak search: the
+                64 x 64 tiles the updates touched are rescanned and the tile
+                maxima reduced; its bytes per iteration (rescanned pixels x 4
+                plus the tile keys) against the full scan's 4 H W, and a
+                check that the residual equals the full-scan run's
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -207,6 +212,44 @@ def smoothing_leg(args, f, rep, secs, rms_plain, torch, asp):
     return out
 
 
+def peak_tiles_leg(args, f, rep, secs, ctx_full, torch, asp):
+    """The timed region's iterations with the incremental peak search."""
+    import numpy as np
+    d_dirty = torch.from_numpy(f.dirty).cuda()
+    d_psf = torch.from_numpy(f.psf).cuda()
+    total = args.warmup + args.steps
+    ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=max(f.max_iter, total),
+                      max_active=f.max_active, fit_solo_tiles=args.solo_tiles,
+                      fit_min_tiles=args.min_tiles, fit_group=args.group, peak_tiles=1)
+    del d_dirty, d_psf
+    ctx.run(args.warmup)
+    ctx.kernel_timing(not args.no_kernel_events)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc, r = ctx.run(args.steps)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t1
+    H, W = f.shape
+    ntiles = ((H + 63) // 64) * ((W + 63) // 64)
+    done = max(r["iterations"], 1)
+    tiles = r["peak_tiles_scanned"] / done
+    bytes_it = tiles * 64 * 64 * 4 + 8 * (ntiles + tiles)
+    out = {"iterations": r["iterations"], "seconds": t_s,
+           "iterations_per_s": r["iterations"] / t_s if t_s > 0 else 0.0,
+           "full_scan_iterations_per_s": rep["iterations"] / secs if secs > 0 else 0.0,
+           "tiles_per_iteration": tiles, "tiles": ntiles,
+           "bytes_per_iteration": bytes_it, "full_scan_bytes_per_iteration": 4.0 * H * W,
+           "same_residual_as_full_scan": bool(np.array_equal(ctx.residual(), ctx_full.residual()))}
+    if not args.no_kernel_events:
+        ms, n = ctx.kernel_times()["peak"]
+        if n:
+            out["peak_us_per_iteration"] = ms / n * 1e3
+            out["achieved_gbs"] = bytes_it / (ms / n * 1e-3) / 1e9
+    log(f"peak tiles {json.dumps(out)}")
+    ctx.close()
+    return out
+
+
 def bench_batch(args):
     """64 independent fields of sizes in {256, 512, 1024, 2048}^2, each with its
     own Gaussian PSF: aggregate iterations/s of one graph-captured persistent
@@ -294,6 +337,8 @@ def main():
     ap.add_argument("--weights", default=None, help="proposal network weights (.npy)")
     ap.add_argument("--no-smoothing", action="store_true",
                     help="skip the smoothing-method (init mode 2) leg")
+    ap.add_argument("--no-peak-tiles", action="store_true",
+                    help="skip the incremental peak search leg")
     ap.add_argument("--probe", type=int, default=5,
                     help="iterations per field of each autotuner probe (batch workload)")
     args = ap.parse_args()
@@ -396,6 +441,10 @@ def main():
     if not args.no_learned and os.path.exists(wpath):
         learned = learned_vs_plain(args, f, wpath, rep, secs, rms_plain, torch, asp)
 
+    peak_tiles = None
+    if not args.no_peak_tiles:
+        peak_tiles = peak_tiles_leg(args, f, rep, secs, ctx, torch, asp)
+
     smoothing = None
     if not args.no_smoothing:
         smoothing = smoothing_leg(args, f, rep, secs, rms_plain, torch, asp)
@@ -427,6 +476,7 @@ def main():
         "hbm": hbm,
         "learned_vs_plain": learned,
         "smoothing": smoothing,
+        "peak_tiles": peak_tiles,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
