@@ -130,7 +130,9 @@ typedef struct {
                                     maximum of |R| of every 64 x 64 tile on the
                                     device and rescans only the tiles that the
                                     residual updates touched (same result)      */
-    int32_t pad0;
+    int32_t refresh_every;       /* > 0: asp_run replaces the residual by the
+                                    exact one (asp_refresh_residual) after every
+                                    refresh_every-th iteration; 0 = never        */
     double window_sigmas;        /* window half-width factor c_w; default 5      */
     double max_width;            /* upper bound on s; 0 = max(omega_b, min(H,W)/8) */
     double lm_mu0;               /* initial damping; default 1e-3                */
@@ -308,6 +310,21 @@ asp_status asp_smooth_peak(asp_ctx *ctx, int32_t *scale, int64_t *idx, float *sc
                            asp_gauss *start);
 asp_status asp_smooth_map(asp_ctx *ctx, int32_t scale, float *out);
 asp_status asp_smooth_widths(asp_ctx *ctx, double *sigma, int32_t cap, int32_t *n);
+/*
+ * Exact-PSF residual refresh (Sect. 2 step 3): R = I_dirty - B (*) I_model with
+ * the true PSF B, instead of the residual the minor cycle keeps by subtracting
+ * each component's Gaussian main-lobe approximation.  The model image holds
+ * every component with its Eq. 5-6 parameters: components at least 1 px wide
+ * as Gaussians sampled at pixel centres on the window of half-width
+ * max(3, ceil(c_w omega)); narrower ones (points included) spread by
+ * band-limited interpolation (per axis the 3-point Gauss-Hermite nodes of the
+ * Gaussian, each with the Lanczos-3 kernel, weights normalised to sum 1).
+ * The convolution is linear, zero outside the image, with the PSF centred on
+ * its peak pixel, computed in FP64 through FFTs of a zero-padded grid; R is
+ * rounded to FP32.  Needs no particular phase; the component list is kept.
+ */
+asp_status asp_refresh_residual(asp_ctx *ctx);
+
 /* Work of the smoothing passes since the context was created: output pixels
  * inside the image summed over both passes and all scales, and the
  * multiply-adds they stand for, 2 (2 h_j + 1) flops per pixel of scale j. */
@@ -402,13 +419,15 @@ asp_status asp_batch_run(asp_batch *batch, int64_t n_iter, asp_batch_report *rep
 asp_status asp_batch_autotune(asp_batch *batch, int64_t probe_iter, int32_t *team_size,
                               int32_t *solo_tiles, int32_t *min_tiles);
 
-/* Diagnostics: per-kernel device time.  With timing on, asp_run, asp_step
- * and asp_smooth_peak record a HIP event pair on the context's stream around
- * every launch they make (which adds two event packets per launch);
- * asp_kernel_times returns the summed milliseconds and launch counts, n <= 6
- * kinds: 0 peak search, 1 LM fit, 2 residual update, 3 proposal / patch
- * recording, 4 the smoothing passes (column and row pass together), 5 the
- * smoothing pick.  Switching timing on or off clears the totals. */
+/* Diagnostics: per-kernel device time.  With timing on, asp_run, asp_step,
+ * asp_smooth_peak and asp_refresh_residual record a HIP event pair on the
+ * context's stream around every launch they make (which adds two event
+ * packets per launch); asp_kernel_times returns the summed milliseconds and
+ * launch counts, n <= 7 kinds: 0 peak search, 1 LM fit, 2 residual update,
+ * 3 proposal / patch recording, 4 the smoothing passes (column and row pass
+ * together), 5 the smoothing pick, 6 the exact-PSF refresh (rendering, two
+ * FFTs, spectral product, subtraction).  Switching timing on or off clears
+ * the totals. */
 asp_status asp_kernel_timing(asp_ctx *ctx, int32_t on);
 asp_status asp_kernel_times(asp_ctx *ctx, double *ms, int64_t *launches, int32_t n);
 

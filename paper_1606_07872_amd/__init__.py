@@ -31,7 +31,7 @@ EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destro
            "asp_mlp_weights", "asp_residual_sumsq", "asp_batch_create", "asp_batch_destroy",
            "asp_batch_last_error", "asp_batch_field", "asp_batch_config", "asp_batch_get_config",
            "asp_batch_run", "asp_batch_autotune", "asp_smooth_peak", "asp_smooth_map",
-           "asp_smooth_widths", "asp_smooth_work"]
+           "asp_smooth_widths", "asp_smooth_work", "asp_refresh_residual"]
 
 MLP_PARAMS = 329220
 MLP_IN = 1024
@@ -51,7 +51,7 @@ class Options(ctypes.Structure):
                 ("fit_solo_tiles", ctypes.c_int32), ("fit_min_tiles", ctypes.c_int32),
                 ("fit_group", ctypes.c_int32), ("smooth_scales", ctypes.c_int32),
                 ("smooth_norm", ctypes.c_int32), ("switch_area", ctypes.c_int32),
-                ("peak_tiles", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("peak_tiles", ctypes.c_int32), ("refresh_every", ctypes.c_int32),
                 ("window_sigmas", ctypes.c_double), ("max_width", ctypes.c_double),
                 ("lm_mu0", ctypes.c_double), ("lm_tol", ctypes.c_double),
                 ("psf_lobe_frac", ctypes.c_double), ("stream", ctypes.c_void_p)]
@@ -163,6 +163,7 @@ def lib():
         L.asp_smooth_map.argtypes = [vp, i32, vp]
         L.asp_smooth_widths.argtypes = [vp, vp, i32, P(i32)]
         L.asp_smooth_work.argtypes = [vp, P(i64), P(f64)]
+        L.asp_refresh_residual.argtypes = [vp]
         for name in EXPORTS:
             if name not in ("asp_destroy", "asp_last_error", "asp_mlp_destroy",
                             "asp_mlp_last_error", "asp_batch_destroy", "asp_batch_last_error"):
@@ -311,7 +312,8 @@ class Context:
         self._check(lib().asp_fit_profile(self._ctx, out.ctypes.data, len(out)))
         return dict(zip(self.PROFILE_FIELDS, out.tolist()))
 
-    KERNEL_KINDS = ("peak", "fit", "update", "propose", "smooth_passes", "smooth_pick")
+    KERNEL_KINDS = ("peak", "fit", "update", "propose", "smooth_passes", "smooth_pick",
+                    "refresh")
 
     def kernel_timing(self, on: bool):
         """Record HIP events around every launch of run()/step() (clears totals)."""
@@ -351,6 +353,10 @@ class Context:
         out = np.empty((self.H, self.W), dtype=np.float32)
         self._check(lib().asp_smooth_map(self._ctx, int(scale), out.ctypes.data))
         return out
+
+    def refresh_residual(self):
+        """Replace the residual by I_dirty - B (*) I_model with the true PSF."""
+        self._check(lib().asp_refresh_residual(self._ctx))
 
     def smooth_work(self):
         """(pixels, flops) of the smoothing passes since creation."""

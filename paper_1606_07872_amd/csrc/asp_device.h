@@ -255,6 +255,27 @@ hipError_t launch_smooth_passes(const Params &p, int force, hipStream_t s);
 hipError_t launch_smooth_pick(const Params &p, int force, hipStream_t s);
 // Every tile of every scale stale, both passes.
 hipError_t launch_smooth_mark_all(const Params &p, hipStream_t s);
+// The exact-PSF residual refresh: its own argument block (the launch
+// parameters of the minor cycle stay within 512 bytes).  grid: Py x Px FP64,
+// the zero-padded model and then the convolution; spec / pspec: Py x
+// (Px / 2 + 1) complex spectra of the model and of the PSF.
+struct RefreshArgs {
+    const float *dirty, *psf;
+    float *R;
+    const double *ca, *cx, *cy, *cs;
+    DevState *st;
+    double *grid;
+    double2 *spec;
+    double2 *pspec;
+    int64_t H, W, Hp, Wp, Py, Px;
+    int32_t ci, cj;                // the PSF's peak pixel
+    double window_sigmas;
+    int32_t force;                 // 1: also when the stop flag is set
+    int32_t pad;
+};
+hipError_t refresh_psf_spectrum(const RefreshArgs &a, void *plan_fwd, hipStream_t s);
+hipError_t refresh_residual(const RefreshArgs &a, void *plan_fwd, void *plan_inv, hipStream_t s);
+
 // The incremental peak search: rescan the stale tiles, then reduce the tile
 // keys into the peak key; and every tile stale.
 hipError_t launch_peak_tiles(const Params &p, int ntiles, hipStream_t s);

@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <hipfft/hipfft.h>
+
 #include "asp_device.h"
 
 using asp::DevState;
@@ -39,8 +41,8 @@ struct asp_ctx {
     bool timing = false;
     std::vector<hipEvent_t> events;       // 2 per launch slot
     std::vector<int> ev_kind;             // kind of each recorded pair
-    double t_ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int64_t t_n[6] = {0, 0, 0, 0, 0, 0};
+    double t_ms[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t t_n[7] = {0, 0, 0, 0, 0, 0, 0};
     // the proposal network (input-major layout) and training-sample recording
     float *net = nullptr;
     asp::NetParams netp{};
@@ -55,6 +57,14 @@ struct asp_ctx {
     int32_t *pk_dirty = nullptr;
     unsigned int *pk_count = nullptr;
     int pk_tiles = 0;                     // > 0: the incremental peak search is on
+    // the exact-PSF refresh: the dirty image kept from creation, the padded
+    // grid and spectra, the FFT plans (made on first use)
+    float *dirty0 = nullptr;
+    double *rf_grid = nullptr;
+    double2 *rf_spec = nullptr, *rf_pspec = nullptr;
+    hipfftHandle rf_fwd = 0, rf_inv = 0;
+    bool rf_ready = false;
+    asp::RefreshArgs rf{};
     bool in_batch = false;                // a field of an asp_batch
     std::string err;
 };
@@ -99,6 +109,10 @@ void release(asp_ctx *c)
     (void)hipFree(c->sm_map); (void)hipFree(c->sm_keys); (void)hipFree(c->sm_dirty);
     (void)hipFree(c->sm_list); (void)hipFree(c->sm_count);
     (void)hipFree(c->pk_keys); (void)hipFree(c->pk_dirty); (void)hipFree(c->pk_count);
+    if (c->rf_fwd) (void)hipfftDestroy(c->rf_fwd);
+    if (c->rf_inv) (void)hipfftDestroy(c->rf_inv);
+    (void)hipFree(c->dirty0); (void)hipFree(c->rf_grid); (void)hipFree(c->rf_spec);
+    (void)hipFree(c->rf_pspec);
     if (c->st_host) (void)hipHostFree(c->st_host);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -266,7 +280,7 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
         opt.lm_max_iter < 1 || opt.init_mode < 0 || opt.init_mode > 2 || opt.capacity < 0 ||
         opt.smooth_scales < 0 || opt.smooth_scales > ASP_MAX_SCALES || opt.smooth_norm < 0 ||
         opt.smooth_norm > 1 || opt.switch_area < 0 || opt.switch_area > 1 || opt.peak_tiles < 0 ||
-        opt.peak_tiles > 1 ||
+        opt.peak_tiles > 1 || opt.refresh_every < 0 ||
         opt.fit_solo_tiles < -1 || opt.fit_min_tiles < 0 || opt.fit_group < 0 ||
         !(opt.window_sigmas > 0.0) || !(opt.max_width >= 0.0) || !(opt.lm_mu0 > 0.0) ||
         !(opt.lm_tol > 0.0) || !(opt.psf_lobe_frac > 0.0 && opt.psf_lobe_frac < 1.0))
@@ -305,6 +319,7 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
         fit_setup_done = true;
     }
     CREATE_HIP(dev_alloc(&c->R, n));
+    CREATE_HIP(dev_alloc(&c->dirty0, n));
     CREATE_HIP(dev_alloc(&c->psf, np));
     CREATE_HIP(dev_alloc(&c->ca, c->cap));
     CREATE_HIP(dev_alloc(&c->cx, c->cap));
@@ -323,6 +338,7 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     const hipMemcpyKind kd = dirty_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     const hipMemcpyKind kp = psf_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     CREATE_HIP(hipMemcpyAsync(c->R, dirty, sizeof(float) * n, kd, c->stream));
+    CREATE_HIP(hipMemcpyAsync(c->dirty0, dirty, sizeof(float) * n, kd, c->stream));
     CREATE_HIP(hipMemcpyAsync(c->psf, psf, sizeof(float) * np, kp, c->stream));
     memset(c->st_host, 0, sizeof(DevState));
     c->st_host->forced_idx = -1;
@@ -455,6 +471,79 @@ asp_status harvest(asp_ctx *c)
 }
 
 bool use_net(const asp_ctx *c) { return c->opt.init_mode == 1 && c->net; }
+
+// The smallest size >= n whose prime factors are 2, 3, 5 and 7 (fast FFTs).
+int64_t fft_size(int64_t n)
+{
+    for (int64_t m = n > 1 ? n : 1;; ++m) {
+        int64_t r = m;
+        for (int64_t f : {2, 3, 5, 7})
+            while (r % f == 0) r /= f;
+        if (r == 1) return m;
+    }
+}
+
+const char *fft_text(hipfftResult r)
+{
+    return r == HIPFFT_SUCCESS ? "ok" : "hipFFT call failed";
+}
+
+// Buffers, plans and the PSF's spectrum of the exact-PSF refresh (first use).
+asp_status setup_refresh(asp_ctx *c)
+{
+    if (c->rf_ready) return ASP_OK;
+    const int64_t H = c->H, W = c->W, Hp = c->Hp, Wp = c->Wp;
+    std::vector<float> ph((size_t)(Hp * Wp));
+    HIP_OR_FAIL(c, hipMemcpyAsync(ph.data(), c->psf, sizeof(float) * ph.size(),
+                                  hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    size_t best = 0;                        // the peak pixel: largest value, lowest index
+    for (size_t i = 1; i < ph.size(); ++i)
+        if (ph[i] > ph[best]) best = i;
+    const int64_t Py = fft_size(H + Hp - 1), Px = fft_size(W + Wp - 1);
+    const size_t nspec = (size_t)Py * (size_t)(Px / 2 + 1);
+    HIP_OR_FAIL(c, dev_alloc(&c->rf_grid, (size_t)(Py * Px)));
+    HIP_OR_FAIL(c, dev_alloc(&c->rf_spec, nspec));
+    HIP_OR_FAIL(c, dev_alloc(&c->rf_pspec, nspec));
+    hipfftResult r = hipfftPlan2d(&c->rf_fwd, (int)Py, (int)Px, HIPFFT_D2Z);
+    if (r == HIPFFT_SUCCESS) r = hipfftPlan2d(&c->rf_inv, (int)Py, (int)Px, HIPFFT_Z2D);
+    if (r == HIPFFT_SUCCESS) r = hipfftSetStream(c->rf_fwd, c->stream);
+    if (r == HIPFFT_SUCCESS) r = hipfftSetStream(c->rf_inv, c->stream);
+    if (r != HIPFFT_SUCCESS) return fail(c, ASP_ERR_DEVICE, std::string("refresh plans: ") + fft_text(r));
+    asp::RefreshArgs &a = c->rf;
+    a.dirty = c->dirty0;
+    a.psf = c->psf;
+    a.R = c->R;
+    a.ca = c->ca; a.cx = c->cx; a.cy = c->cy; a.cs = c->cs;
+    a.st = c->st;
+    a.grid = c->rf_grid;
+    a.spec = c->rf_spec;
+    a.pspec = c->rf_pspec;
+    a.H = H; a.W = W; a.Hp = Hp; a.Wp = Wp; a.Py = Py; a.Px = Px;
+    a.ci = (int32_t)(best / (size_t)Wp);
+    a.cj = (int32_t)(best % (size_t)Wp);
+    a.window_sigmas = c->opt.window_sigmas;
+    a.force = 1;
+    HIP_OR_FAIL(c, asp::refresh_psf_spectrum(a, &c->rf_fwd, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->rf_ready = true;
+    return ASP_OK;
+}
+
+// One refresh on the stream; then every tile of the incremental searches is
+// stale (the whole residual changed).
+asp_status enqueue_refresh(asp_ctx *c, int force)
+{
+    asp::RefreshArgs a = c->rf;
+    a.force = force;
+    asp_status s = timed(c, 6, [&] {
+        return asp::refresh_residual(a, &c->rf_fwd, &c->rf_inv, c->stream);
+    });
+    if (s != ASP_OK) return s;
+    if (c->pk_tiles) HIP_OR_FAIL(c, asp::launch_peak_mark_all(c->P, c->stream));
+    if (c->P.sm.n > 0) HIP_OR_FAIL(c, asp::launch_smooth_mark_all(c->P, c->stream));
+    return ASP_OK;
+}
 
 asp_status enqueue_iteration(asp_ctx *c)
 {
@@ -615,8 +704,20 @@ asp_status asp_step(asp_ctx *c)
 {
     if (!c) return ASP_ERR_INVALID_ARG;
     if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_step inside a step-API sequence");
-    asp_status s = enqueue_iteration(c);
+    const int every = c->opt.refresh_every;
+    if (every > 0) {
+        asp_status r = setup_refresh(c);
+        if (r != ASP_OK) return r;
+    }
+    asp_status s = pull_all(c);
     if (s != ASP_OK) return s;
+    const int64_t k = c->st_host->k;
+    s = enqueue_iteration(c);
+    if (s != ASP_OK) return s;
+    if (every > 0 && (k + 1) % every == 0) {
+        s = enqueue_refresh(c, 0);
+        if (s != ASP_OK) return s;
+    }
     s = pull_all(c);
     if (s != ASP_OK) return s;
     s = harvest(c);
@@ -635,13 +736,25 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
                              fb0 = c->st_host->fallbacks, up0 = c->st_host->sum_update_px,
                              ep0 = c->st_host->sum_eval_px, gf0 = c->st_host->sum_gram_flops,
                              sm0 = c->st_host->sum_smoothed, pk0 = c->st_host->pk_tiles_done;
+    const int every = c->opt.refresh_every;
+    if (every > 0) {
+        s = setup_refresh(c);
+        if (s != ASP_OK) return s;
+    }
     int64_t done = 0;
     asp_status result = stop_status(c);
     while (result == ASP_OK && done < n_iter) {
         const int64_t chunk = (n_iter - done) < 256 ? (n_iter - done) : 256;
+        const int64_t kc = c->st_host->k;
         for (int64_t i = 0; i < chunk; ++i) {
             s = enqueue_iteration(c);
             if (s != ASP_OK) return s;
+            // the exact-PSF refresh after every `every`-th iteration (a refresh
+            // queued behind a stop leaves the residual alone)
+            if (every > 0 && (kc + i + 1) % every == 0) {
+                s = enqueue_refresh(c, 0);
+                if (s != ASP_OK) return s;
+            }
         }
         s = pull_all(c);
         if (s != ASP_OK) return s;
@@ -775,13 +888,13 @@ asp_status asp_kernel_timing(asp_ctx *c, int32_t on)
         if (s != ASP_OK) return s;
     }
     c->timing = on != 0;
-    for (int i = 0; i < 6; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
+    for (int i = 0; i < 7; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
     return ASP_OK;
 }
 
 asp_status asp_kernel_times(asp_ctx *c, double *ms, int64_t *launches, int32_t n)
 {
-    if (!c || n < 0 || n > 6 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
+    if (!c || n < 0 || n > 7 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i) { ms[i] = c->t_ms[i]; launches[i] = c->t_n[i]; }
     return ASP_OK;
 }
@@ -870,6 +983,17 @@ asp_status asp_smooth_map(asp_ctx *c, int32_t scale, float *out)
                                   hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     return ASP_OK;
+}
+
+asp_status asp_refresh_residual(asp_ctx *c)
+{
+    if (!c) return ASP_ERR_INVALID_ARG;
+    if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_refresh_residual inside a step-API sequence");
+    asp_status s = setup_refresh(c);
+    if (s == ASP_OK) s = enqueue_refresh(c, 1);
+    if (s == ASP_OK) s = pull_all(c);
+    if (s == ASP_OK) s = harvest(c);
+    return s;
 }
 
 asp_status asp_smooth_work(asp_ctx *c, int64_t *pixels, double *flops)
@@ -1062,8 +1186,8 @@ asp_status asp_batch_create(int32_t n_fields, const float *const *dirty, const i
         o = *opt;
     }
     o.stream = b->stream;
-    // the batched kernel has its own peak scan and no smoothing method
-    if (o.init_mode == 2 || o.peak_tiles) return bail(ASP_ERR_INVALID_ARG);
+    // the batched kernel has its own peak scan, no smoothing method and no refresh
+    if (o.init_mode == 2 || o.peak_tiles || o.refresh_every) return bail(ASP_ERR_INVALID_ARG);
     for (int32_t i = 0; i < n_fields; ++i) {
         asp_ctx *c = nullptr;
         asp_status s = asp_create(dirty[i], H[i], W[i], psf[i], Hp[i], Wp[i], gain[i],
