@@ -30,6 +30,10 @@ Besides the throughput the line carries:
                 maxima reduced; its bytes per iteration (rescanned pixels x 4
                 plus the tile keys) against the full scan's 4 H W, and a
                 check that the residual equals the full-scan run's
+  refresh       the exact-PSF residual refresh (R = I_dirty - B (*) I_model):
+                the time of one refresh, and the same iterations run with a
+                refresh after every 500th; the true residual (refreshed once
+                more at the end) of both runs
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -250,6 +254,45 @@ def peak_tiles_leg(args, f, rep, secs, ctx_full, torch, asp):
     return out
 
 
+def refresh_leg(args, f, rep, secs, ctx_plain, torch, asp):
+    """The exact-PSF refresh: cost and effect on the true residual."""
+    total = args.warmup + args.steps
+    every = 500
+    d_dirty = torch.from_numpy(f.dirty).cuda()
+    d_psf = torch.from_numpy(f.psf).cuda()
+    ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=max(f.max_iter, total),
+                      max_active=f.max_active, fit_solo_tiles=args.solo_tiles,
+                      fit_min_tiles=args.min_tiles, fit_group=args.group, refresh_every=every)
+    del d_dirty, d_psf
+    ctx.run(args.warmup)
+    ctx.kernel_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc, r = ctx.run(args.steps)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t1
+    ms, n = ctx.kernel_times()["refresh"]
+    rms_minor = ctx.residual_rms()
+    ctx.refresh_residual()
+    rms_true = ctx.residual_rms()
+    ctx.close()
+    # the plain run's residual against its exact one (the plain context is not
+    # used after this leg)
+    rms_plain_minor = ctx_plain.residual_rms()
+    ctx_plain.kernel_timing(True)
+    ctx_plain.refresh_residual()
+    pms, pn = ctx_plain.kernel_times()["refresh"]
+    rms_plain_true = ctx_plain.residual_rms()
+    out = {"every": every, "iterations": r["iterations"], "seconds": t_s,
+           "iterations_per_s": r["iterations"] / t_s if t_s > 0 else 0.0,
+           "plain_iterations_per_s": rep["iterations"] / secs if secs > 0 else 0.0,
+           "refreshes": n, "ms_per_refresh": ms / n if n else (pms / pn if pn else None),
+           "rms_minor_cycle": rms_minor, "rms_true": rms_true,
+           "plain_rms_minor_cycle": rms_plain_minor, "plain_rms_true": rms_plain_true}
+    log(f"refresh {json.dumps(out)}")
+    return out
+
+
 def bench_batch(args):
     """64 independent fields of sizes in {256, 512, 1024, 2048}^2, each with its
     own Gaussian PSF: aggregate iterations/s of one graph-captured persistent
@@ -339,6 +382,8 @@ def main():
                     help="skip the smoothing-method (init mode 2) leg")
     ap.add_argument("--no-peak-tiles", action="store_true",
                     help="skip the incremental peak search leg")
+    ap.add_argument("--no-refresh", action="store_true",
+                    help="skip the exact-PSF refresh leg")
     ap.add_argument("--probe", type=int, default=5,
                     help="iterations per field of each autotuner probe (batch workload)")
     args = ap.parse_args()
@@ -449,6 +494,10 @@ def main():
     if not args.no_smoothing:
         smoothing = smoothing_leg(args, f, rep, secs, rms_plain, torch, asp)
 
+    refresh = None
+    if not args.no_refresh:
+        refresh = refresh_leg(args, f, rep, secs, ctx, torch, asp)
+
     cpu = None
     if want_cpu:
         log(f"oracle baseline for {args.cpu_seconds:.0f}s from iteration {k0}")
@@ -477,6 +526,7 @@ def main():
         "learned_vs_plain": learned,
         "smoothing": smoothing,
         "peak_tiles": peak_tiles,
+        "refresh": refresh,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
