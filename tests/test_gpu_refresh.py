@@ -5,7 +5,7 @@ given the GPU's own component list.
 The GPU renders and convolves in FP64 and rounds R to FP32, so the bound is
 the FP32 rounding of the result plus the FP64 FFT error: |dR| <= 2^-23
 max(|D|, |B (*) M|) + 1e-9 max|D| elementwise (the model's FP64 sums are
-accumulated by atomics, in no fixed order)."""
+taken in another order than the oracle's)."""
 import numpy as np
 import pytest
 
