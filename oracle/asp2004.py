@@ -21,25 +21,29 @@ iteration
 
 Readings where the paper is silent (each listed in the design notes):
 
-* The parameters are theta = (F, x, y, omega): flux, centre, width of the sky
-  component.  The component image g(theta) is rendered as the exact-PSF
-  refresh renders the model (``oracle/refresh.py``): a sampled Gaussian for
-  omega >= 1 px, Gauss-Hermite nodes spread by Lanczos-3 below.  The Jacobian
-  columns are B (*) dg/dtheta_k with the derivatives of that rendering taken
-  analytically in the regime of the current omega.
+* The parameters are theta = (F, x, y, v): flux, centre and the squared width
+  v = omega^2 of the sky component.  The component image g(theta) is rendered
+  as the exact-PSF refresh renders the model (``oracle/refresh.py``): a
+  sampled Gaussian for omega >= 1 px, Gauss-Hermite nodes spread by Lanczos-3
+  below.  That rendering is even in omega, so its derivative in omega vanishes
+  at a point source and a fit there cannot leave the bound omega = 0; in v the
+  derivative is finite and in general not zero (at v = 0 it is half the
+  second derivative of the profile).  The Jacobian columns are
+  B (*) dg/dtheta_k with the derivatives of the rendering taken analytically
+  in the regime of the current width.
 * One component is fitted per iteration (the paper's cost count is for a
   single component); the earlier ones stay fixed.
 * Start: from the smoothing start (a_c, col, row, sigma_j) in convolved space,
-  omega_0 = sqrt(max(sigma_j^2 - omega_b^2, 0)) and, by Eq. 5,
+  v_0 = max(sigma_j^2 - omega_b^2, 0) and, by Eq. 5,
   F_0 = a_c sigma_j^2 / (alpha_b omega_b^2).
 * Bounds: F keeps the start's sign; x and y stay in the window of the start
-  (half-width max(3, ceil(c_w s_0)), s_0 = sqrt(omega_0^2 + omega_b^2)); omega in
-  [0, sqrt(max(s_max^2 - omega_b^2, 0))], s_max the width bound of the
+  (half-width max(3, ceil(c_w s_0)), s_0 = sqrt(v_0 + omega_b^2)); v in
+  [0, max(s_max^2 - omega_b^2, 0)], s_max the width bound of the
   Asp-Clean2016 fit.
 * LM: the rules of the Asp-Clean2016 fit (the C oracle's ``lm_fit``) restated
   for four parameters, with F(theta) = sum over the image of m (m - 2 R),
   m = B (*) g(theta), which is chi^2 less the constant sum of R^2; the step
-  test scales x, y and omega by sqrt(omega^2 + omega_b^2).
+  test scales x and y by s = sqrt(v + omega_b^2) and v by s^2.
 * The component is kept in the list in convolved-space form, the Gaussian
   (a, s) whose Eqs. 5-6 deconvolution is (gain F, omega), so the reported
   components and the exact-PSF refresh read it like any other.
@@ -54,6 +58,7 @@ from . import refresh as rf
 from . import smoothing as sm
 
 MU_MIN, MU_MAX = 1e-12, 1e8
+SMALL_WIDTH = 1e-4               # px: below, dg/dv takes its limit at omega = 0
 
 
 # ---------------------------------------------------------------------------
@@ -73,6 +78,19 @@ def _dsinc(t: np.ndarray) -> np.ndarray:
     return out
 
 
+def _d2sinc(t: np.ndarray) -> np.ndarray:
+    """d^2/dt^2 of sin(pi t) / (pi t)."""
+    t = np.asarray(t, dtype=np.float64)
+    out = np.empty_like(t)
+    small = np.abs(t) < 1e-3
+    ts = t[small]
+    pi2 = math.pi * math.pi
+    out[small] = -pi2 / 3.0 + pi2 * pi2 * ts * ts / 10.0
+    tb = t[~small]
+    out[~small] = -pi2 * np.sinc(tb) - 2.0 * _dsinc(tb) / tb
+    return out
+
+
 def lanczos_deriv(t: np.ndarray) -> np.ndarray:
     """d/dt of the Lanczos-3 kernel sinc(t) sinc(t/3), zero for |t| >= 3."""
     t = np.asarray(t, dtype=np.float64)
@@ -80,55 +98,70 @@ def lanczos_deriv(t: np.ndarray) -> np.ndarray:
     return np.where(np.abs(t) < rf.LANCZOS_A, d, 0.0)
 
 
-def _axis(x: float, omega: float):
-    """First pixel, normalised weights w and dw/dx, dw/domega of one axis of the
-    interpolated profile (the refresh's narrow-component rendering)."""
+def lanczos_deriv2(t: np.ndarray) -> np.ndarray:
+    """d^2/dt^2 of the Lanczos-3 kernel, zero for |t| >= 3."""
+    t = np.asarray(t, dtype=np.float64)
+    u = t / 3.0
+    d = (_d2sinc(t) * np.sinc(u) + 2.0 * _dsinc(t) * _dsinc(u) / 3.0 +
+         np.sinc(t) * _d2sinc(u) / 9.0)
+    return np.where(np.abs(t) < rf.LANCZOS_A, d, 0.0)
+
+
+def _axis(x: float, v: float):
+    """First pixel, normalised weights w and dw/dx, dw/dv (v = omega^2) of one
+    axis of the interpolated profile (the refresh's narrow-component
+    rendering)."""
+    omega = math.sqrt(v)
     c0 = int(math.floor(x)) - 5
     cs = np.arange(c0, c0 + 12, dtype=np.float64)
     u = np.zeros_like(cs)
     ux = np.zeros_like(cs)
-    uw = np.zeros_like(cs)
+    uv = np.zeros_like(cs)
     for d, p in zip(rf.GH_OFFSETS, rf.GH_WEIGHTS):
         t = cs - x - d * omega
         u += p * rf.lanczos(t)
         ld = lanczos_deriv(t)
         ux -= p * ld
-        uw -= p * d * ld
+        if omega >= SMALL_WIDTH:
+            uv -= p * d * ld / (2.0 * omega)
+    if omega < SMALL_WIDTH:
+        # the limit: sum_k p_k d_k^2 L''(t) / 2, and sum_k p_k d_k^2 = 1
+        uv = 0.5 * lanczos_deriv2(cs - x)
     S = u.sum()
     w = u / S
     wx = (ux - w * ux.sum()) / S
-    ww = (uw - w * uw.sum()) / S
-    return c0, w, wx, ww
+    wv = (uv - w * uv.sum()) / S
+    return c0, w, wx, wv
 
 
-def unit_images(shape, x: float, y: float, omega: float, window_sigmas: float = 5.0):
-    """(g, dg/dx, dg/dy, dg/domega) of the unit-flux component at (x, y) of
-    width omega on the H x W grid, zero outside its footprint."""
+def unit_images(shape, x: float, y: float, v: float, window_sigmas: float = 5.0):
+    """(g, dg/dx, dg/dy, dg/dv) of the unit-flux component at (x, y) of squared
+    width v on the H x W grid, zero outside its footprint."""
     H, W = shape
     g = np.zeros((H, W))
     gx = np.zeros((H, W))
     gy = np.zeros((H, W))
-    gw = np.zeros((H, W))
+    gv = np.zeros((H, W))
+    omega = math.sqrt(v)
     if omega >= rf.RENDER_MIN_WIDTH:
         h = rf.halfwidth(omega, window_sigmas)
         cx, cy = int(math.floor(x + 0.5)), int(math.floor(y + 0.5))
         r0, r1 = max(0, cy - h), min(H - 1, cy + h)
         c0, c1 = max(0, cx - h), min(W - 1, cx + h)
         if r0 > r1 or c0 > c1:
-            return g, gx, gy, gw
+            return g, gx, gy, gv
         dy = np.arange(r0, r1 + 1, dtype=np.float64)[:, None] - y
         dx = np.arange(c0, c1 + 1, dtype=np.float64)[None, :] - x
         q = dx * dx + dy * dy
-        w2 = omega * omega
-        e = np.exp(-q / (2.0 * w2)) / (2.0 * math.pi * w2)
+        e = np.exp(-q / (2.0 * v)) / (2.0 * math.pi * v)
         sl = (slice(r0, r1 + 1), slice(c0, c1 + 1))
         g[sl] = e
-        gx[sl] = e * dx / w2
-        gy[sl] = e * dy / w2
-        gw[sl] = e * (q / (w2 * omega) - 2.0 / omega)
-        return g, gx, gy, gw
-    cx0, wx, dwx, wwx = _axis(x, omega)
-    cy0, wy, dwy, wwy = _axis(y, omega)
+        gx[sl] = e * dx / v
+        gy[sl] = e * dy / v
+        gv[sl] = e * (q / (2.0 * v * v) - 1.0 / v)
+        return g, gx, gy, gv
+    cx0, wx, dwx, wvx = _axis(x, v)
+    cy0, wy, dwy, wvy = _axis(y, v)
     for i in range(12):
         r = cy0 + i
         if r < 0 or r >= H:
@@ -140,8 +173,8 @@ def unit_images(shape, x: float, y: float, omega: float, window_sigmas: float = 
             g[r, c] = wy[i] * wx[j]
             gx[r, c] = wy[i] * dwx[j]
             gy[r, c] = dwy[i] * wx[j]
-            gw[r, c] = wwy[i] * wx[j] + wy[i] * wwx[j]
-    return g, gx, gy, gw
+            gv[r, c] = wvy[i] * wx[j] + wy[i] * wvx[j]
+    return g, gx, gy, gv
 
 
 # ---------------------------------------------------------------------------
@@ -160,15 +193,15 @@ class Problem:
 
     def convolved(self, theta):
         """B (*) g(theta) (with its flux)."""
-        F, x, y, om = (float(v) for v in theta)
-        g = unit_images(self.R.shape, x, y, om, self.ws)[0]
+        F, x, y, v = (float(t) for t in theta)
+        g = unit_images(self.R.shape, x, y, v, self.ws)[0]
         return F * rf.convolve_psf(g, self.psf)
 
     def evaluate(self, theta, want_jac: bool = True):
         """(F(theta), chi^2, J^T J, J^T r) with F = sum m (m - 2 R), r = R - m."""
         self.evaluations += 1
-        F, x, y, om = (float(v) for v in theta)
-        imgs = unit_images(self.R.shape, x, y, om, self.ws)
+        F, x, y, v = (float(t) for t in theta)
+        imgs = unit_images(self.R.shape, x, y, v, self.ws)
         conv = [rf.convolve_psf(im, self.psf) for im in (imgs if want_jac else imgs[:1])]
         m = F * conv[0]
         r = self.R - m
@@ -210,8 +243,9 @@ def lm_fit(prob: Problem, theta0, lo, hi, budget: int = 100, mu0: float = 1e-3,
     bound with its gradient pointing out is held for the trial; the trial is
     clipped to the bounds and accepted iff F decreases; gain-ratio damping
     (Madsen, Nielsen & Tingleff); converged on an accepted step with
-    max |delta_k| / scale_k < tol, or stalled once mu passes 1e8; the budget
-    counts trials."""
+    max |delta_k| / scale_k < tol (scales |F|, s, s, s^2 with
+    s = sqrt(v + omega_b^2)), or stalled once mu passes 1e8; the budget counts
+    trials."""
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
     theta = np.clip(np.asarray(theta0, dtype=np.float64), lo, hi)
@@ -240,10 +274,11 @@ def lm_fit(prob: Problem, theta0, lo, hi, budget: int = 100, mu0: float = 1e-3,
             if not math.isfinite(Ft):
                 Ft = math.inf
         if Ft < Fv:
-            st = math.sqrt(trial[3] * trial[3] + prob.omega_b * prob.omega_b)
+            s2 = trial[3] + prob.omega_b * prob.omega_b
+            st = math.sqrt(s2)
             sa = max(abs(trial[0]), 1e-30)
             step = max(abs(trial[0] - theta[0]) / sa, abs(trial[1] - theta[1]) / st,
-                       abs(trial[2] - theta[2]) / st, abs(trial[3] - theta[3]) / st)
+                       abs(trial[2] - theta[2]) / st, abs(trial[3] - theta[3]) / s2)
             rho = (Fv - Ft) / pred if pred > 0.0 else 1.0
             t = 2.0 * rho - 1.0
             mu *= max(1.0 / 3.0, 1.0 - t * t * t)
@@ -269,10 +304,11 @@ def lm_fit(prob: Problem, theta0, lo, hi, budget: int = 100, mu0: float = 1e-3,
 # ---------------------------------------------------------------------------
 
 def start_from_smoothing(start4, alpha_b: float, omega_b: float):
-    """Sky-plane (F, x, y, omega) from the smoothing start (a_c, col, row, sigma)."""
+    """Sky-plane (F, x, y, v = omega^2) from the smoothing start (a_c, col, row,
+    sigma)."""
     a_c, x, y, s = (float(v) for v in start4)
-    om = math.sqrt(max(s * s - omega_b * omega_b, 0.0))
-    return np.array([a_c * s * s / (alpha_b * omega_b * omega_b), x, y, om])
+    v = max(s * s - omega_b * omega_b, 0.0)
+    return np.array([a_c * s * s / (alpha_b * omega_b * omega_b), x, y, v])
 
 
 def convolved_form(F: float, omega: float, alpha_b: float, omega_b: float):
@@ -308,15 +344,15 @@ class Oracle2004:
 
     def bounds(self, theta0):
         H, W = self.R.shape
-        s0 = math.sqrt(theta0[3] ** 2 + self.omega_b ** 2)
+        s0 = math.sqrt(theta0[3] + self.omega_b ** 2)
         h = rf.halfwidth(s0, self.ws)
         cx, cy = int(math.floor(theta0[1] + 0.5)), int(math.floor(theta0[2] + 0.5))
         r0, r1 = max(0, cy - h), min(H - 1, cy + h)
         c0, c1 = max(0, cx - h), min(W - 1, cx + h)
         neg = theta0[0] < 0.0
-        om_max = math.sqrt(max(self.s_max ** 2 - self.omega_b ** 2, 0.0))
+        v_max = max(self.s_max ** 2 - self.omega_b ** 2, 0.0)
         lo = [-math.inf if neg else 0.0, float(c0), float(r0), 0.0]
-        hi = [0.0 if neg else math.inf, float(c1), float(r1), om_max]
+        hi = [0.0 if neg else math.inf, float(c1), float(r1), v_max]
         return lo, hi
 
     def step(self, start=None, method=None) -> dict:
@@ -347,7 +383,7 @@ class Oracle2004:
         th = fit["theta"]
         conv = prob.convolved([self.gain * th[0], th[1], th[2], th[3]])
         self.R = R - conv
-        a, s = convolved_form(self.gain * th[0], th[3], self.alpha_b, self.omega_b)
+        a, s = convolved_form(self.gain * th[0], math.sqrt(th[3]), self.alpha_b, self.omega_b)
         self.comps.append([a, float(th[1]), float(th[2]), s])
         self.k += 1
         out.update({"status": "ok" if fit["converged"] else "not_converged",
