@@ -325,6 +325,55 @@ asp_status asp_smooth_widths(asp_ctx *ctx, double *sigma, int32_t cap, int32_t *
  */
 asp_status asp_refresh_residual(asp_ctx *ctx);
 
+/*
+ * The Asp-Clean2004 iteration, the comparison path of the paper (Sect. 2
+ * steps 1-4 with the objective of Eq. 3; the cost count after it; Table 3).
+ *   1. the peak of |residual| and the stop test, as asp_find_peak;
+ *   2. start values from the smoothing method (every iteration; no switch),
+ *      turned into sky-plane values by Eq. 5: omega_0^2 = max(s^2 -
+ *      omega_b^2, 0), F_0 = a s^2 / (alpha_b omega_b^2);
+ *   3. Levenberg-Marquardt fit of the one new component theta = (F, x, y,
+ *      v = omega^2) against chi^2 = || R - B (*) g(theta) ||^2 over the whole
+ *      image with the true PSF B, convolved by FFT (FP64) in every
+ *      evaluation.  g is the unit-flux component rendered as
+ *      asp_refresh_residual renders the model, times F; the squared width
+ *      keeps the objective differentiable at a point source.  Bounds: F keeps
+ *      the start's sign, x and y stay in the start's window,
+ *      0 <= v <= s_max^2 - omega_b^2.  LM rules, budget (lm_max_iter) and
+ *      tolerance are those of asp_fit_active_set;
+ *   4. R -= gain B (*) g(theta) (exact, FP64, rounded to FP32), and the
+ *      component joins the list as the convolved-space Gaussian whose Eqs. 5-6
+ *      deconvolution is (gain F, omega), so asp_components and
+ *      asp_refresh_residual read it like any other.
+ * Earlier components are not refitted.  The host reads the device's LM state
+ * after each evaluation.  The first call allocates four FP64 grids and their
+ * spectra of the refresh's padded size and batched FFT plans.  Must not be
+ * inside a find_peak / fit / update sequence (ASP_ERR_STATE); not available
+ * to batched fields.  Returns ASP_OK, ASP_LM_NOT_CONVERGED (budget used),
+ * ASP_STOP_THRESHOLD or ASP_STOP_MAXITER.  rep may be NULL.
+ */
+typedef struct {
+    int64_t idx;                 /* peak pixel                                   */
+    float peak;                  /* residual there before the fit                */
+    int32_t scale;               /* trial width j of the smoothing start         */
+    int32_t trials;              /* LM trials                                    */
+    int32_t converged;
+    int32_t evaluations;         /* evaluations of Eq. 3 (trials + the start)    */
+    int32_t pad;
+    double start[4];             /* the smoothing start (a, x, y, s), convolved  */
+    double theta0[4];            /* sky (F, x, y, omega^2) start in the bounds   */
+    double theta[4];             /* fitted sky (F, x, y, omega^2), before gain   */
+    double lo[4], hi[4];         /* the bounds                                   */
+    double chi2_init, chi2_final;/* over the whole image                         */
+} asp_fit2004_report;
+
+asp_status asp_step_2004(asp_ctx *ctx, asp_fit2004_report *rep);
+
+/* Up to n_iter Asp-Clean2004 iterations; rep as for asp_run (lm_trials,
+ * not_converged, pixels_evaluated = evaluations x H x W, smoothed).  Returns
+ * ASP_OK (n_iter done), ASP_STOP_THRESHOLD or ASP_STOP_MAXITER. */
+asp_status asp_run_2004(asp_ctx *ctx, int64_t n_iter, asp_run_report *rep);
+
 /* Work of the smoothing passes since the context was created: output pixels
  * inside the image summed over both passes and all scales, and the
  * multiply-adds they stand for, 2 (2 h_j + 1) flops per pixel of scale j. */
@@ -420,14 +469,17 @@ asp_status asp_batch_autotune(asp_batch *batch, int64_t probe_iter, int32_t *tea
                               int32_t *solo_tiles, int32_t *min_tiles);
 
 /* Diagnostics: per-kernel device time.  With timing on, asp_run, asp_step,
- * asp_smooth_peak and asp_refresh_residual record a HIP event pair on the
- * context's stream around every launch they make (which adds two event
- * packets per launch); asp_kernel_times returns the summed milliseconds and
- * launch counts, n <= 7 kinds: 0 peak search, 1 LM fit, 2 residual update,
- * 3 proposal / patch recording, 4 the smoothing passes (column and row pass
- * together), 5 the smoothing pick, 6 the exact-PSF refresh (rendering, two
- * FFTs, spectral product, subtraction).  Switching timing on or off clears
- * the totals. */
+ * asp_smooth_peak, asp_refresh_residual, asp_step_2004 and asp_run_2004
+ * record a HIP event pair on the context's stream around every launch they
+ * make (which adds two event packets per launch); asp_kernel_times returns
+ * the summed milliseconds and launch counts, n <= 9 kinds: 0 peak search,
+ * 1 LM fit, 2 residual update, 3 proposal / patch recording, 4 the smoothing
+ * passes (column and row pass together), 5 the smoothing pick, 6 the
+ * exact-PSF refresh (rendering, two FFTs, spectral product, subtraction),
+ * 7 one evaluation of the Asp-Clean2004 objective (rendering of the component
+ * and its derivatives, the batched FFTs, the sums, the LM decision), 8 the
+ * Asp-Clean2004 update (rendering, two FFTs, subtraction, the new component).
+ * Switching timing on or off clears the totals. */
 asp_status asp_kernel_timing(asp_ctx *ctx, int32_t on);
 asp_status asp_kernel_times(asp_ctx *ctx, double *ms, int64_t *launches, int32_t n);
 

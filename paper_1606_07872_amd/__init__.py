@@ -31,7 +31,8 @@ EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destro
            "asp_mlp_weights", "asp_residual_sumsq", "asp_batch_create", "asp_batch_destroy",
            "asp_batch_last_error", "asp_batch_field", "asp_batch_config", "asp_batch_get_config",
            "asp_batch_run", "asp_batch_autotune", "asp_smooth_peak", "asp_smooth_map",
-           "asp_smooth_widths", "asp_smooth_work", "asp_refresh_residual"]
+           "asp_smooth_widths", "asp_smooth_work", "asp_refresh_residual", "asp_step_2004",
+           "asp_run_2004"]
 
 MLP_PARAMS = 329220
 MLP_IN = 1024
@@ -80,6 +81,16 @@ class FitReport(ctypes.Structure):
                 ("theta", ctypes.c_double * (4 * MAX_ACTIVE)),
                 ("fit_px", ctypes.c_int64), ("init_source", ctypes.c_int32),
                 ("start_from_proposal", ctypes.c_int32), ("init", ctypes.c_double * 4)]
+
+
+class Fit2004Report(ctypes.Structure):
+    _fields_ = [("idx", ctypes.c_int64), ("peak", ctypes.c_float), ("scale", ctypes.c_int32),
+                ("trials", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("evaluations", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("start", ctypes.c_double * 4), ("theta0", ctypes.c_double * 4),
+                ("theta", ctypes.c_double * 4), ("lo", ctypes.c_double * 4),
+                ("hi", ctypes.c_double * 4), ("chi2_init", ctypes.c_double),
+                ("chi2_final", ctypes.c_double)]
 
 
 class BatchReport(ctypes.Structure):
@@ -164,6 +175,8 @@ def lib():
         L.asp_smooth_widths.argtypes = [vp, vp, i32, P(i32)]
         L.asp_smooth_work.argtypes = [vp, P(i64), P(f64)]
         L.asp_refresh_residual.argtypes = [vp]
+        L.asp_step_2004.argtypes = [vp, P(Fit2004Report)]
+        L.asp_run_2004.argtypes = [vp, i64, P(RunReport)]
         for name in EXPORTS:
             if name not in ("asp_destroy", "asp_last_error", "asp_mlp_destroy",
                             "asp_mlp_last_error", "asp_batch_destroy", "asp_batch_last_error"):
@@ -313,7 +326,7 @@ class Context:
         return dict(zip(self.PROFILE_FIELDS, out.tolist()))
 
     KERNEL_KINDS = ("peak", "fit", "update", "propose", "smooth_passes", "smooth_pick",
-                    "refresh")
+                    "refresh", "eval2004", "update2004")
 
     def kernel_timing(self, on: bool):
         """Record HIP events around every launch of run()/step() (clears totals)."""
@@ -357,6 +370,22 @@ class Context:
     def refresh_residual(self):
         """Replace the residual by I_dirty - B (*) I_model with the true PSF."""
         self._check(lib().asp_refresh_residual(self._ctx))
+
+    # -- the Asp-Clean2004 comparison path -------------------------------------
+    def step_2004(self):
+        """One Asp-Clean2004 iteration (Eq. 3 fitted with the true PSF)."""
+        rep = Fit2004Report()
+        rc = self._check(lib().asp_step_2004(self._ctx, ctypes.byref(rep)))
+        out = {}
+        for f, _ in Fit2004Report._fields_:
+            v = getattr(rep, f)
+            out[f] = np.array(v[:]) if isinstance(v, ctypes.Array) else v
+        return rc, out
+
+    def run_2004(self, n_iter: int):
+        rep = RunReport()
+        rc = self._check(lib().asp_run_2004(self._ctx, n_iter, ctypes.byref(rep)))
+        return rc, {f: getattr(rep, f) for f, _ in RunReport._fields_}
 
     def smooth_work(self):
         """(pixels, flops) of the smoothing passes since creation."""

@@ -276,6 +276,48 @@ struct RefreshArgs {
 hipError_t refresh_psf_spectrum(const RefreshArgs &a, void *plan_fwd, hipStream_t s);
 hipError_t refresh_residual(const RefreshArgs &a, void *plan_fwd, void *plan_inv, hipStream_t s);
 
+// The Asp-Clean2004 iteration (Sect. 2 steps 1-4 with the objective of
+// Eq. 3): Levenberg-Marquardt state of the one sky component (F, x, y,
+// omega^2) being fitted, kept on the device between the evaluations.
+struct A4State {
+    double theta[4];               // accepted point
+    double te[4];                  // point under evaluation
+    double theta0[4];              // start after the bounds
+    double lo[4], hi[4];
+    double Hs[16], g[4];           // J^T J and J^T r at theta
+    double dd[4];                  // the damping's diagonal of the last trial
+    double F, chi2, F0, chi2_init; // F = sum m (m - 2 R); chi2 = sum (R - m)^2
+    double mu, nu, pred;
+    int32_t trials, converged, done, phase;   // phase 0: the start is evaluated next
+    int32_t evals, pad;
+};
+constexpr int kA4Sums = 16;        // 10 Gram entries, 4 of J^T r, F, chi2
+constexpr int kA4Blocks = 1024;    // partial rows of an evaluation
+
+struct A4Args {
+    float *R;
+    DevState *st;
+    A4State *s;
+    double *ca, *cx, *cy, *cs;
+    int64_t *c_added, *c_updated;
+    int64_t cap;
+    double *grid;                  // 4 images Py x Px: g, dg/dx, dg/dy, dg/d(omega^2)
+    double2 *spec;                 // their half spectra, Py x (Px/2 + 1) each
+    const double2 *pspec;          // the PSF's
+    double *partials;              // kA4Blocks x kA4Sums
+    int64_t H, W, Py, Px;
+    int32_t ci, cj;                // the PSF's peak pixel
+    int32_t budget, pad;
+    double gain, window_sigmas, s_max, mu0, tol;
+};
+// Stop test after the peak, the start from the smoothing method, bounds.
+hipError_t a4_begin(const A4Args &a, hipStream_t s);
+// One evaluation of Eq. 3 and its Jacobian at s->te, then the LM decision and
+// the next trial point (or done).  plan_fwd / plan_inv: batched (4) D2Z / Z2D.
+hipError_t a4_trial(const A4Args &a, void *plan_fwd4, void *plan_inv4, hipStream_t s);
+// The residual update R -= gain B (*) g(theta) and the new component.
+hipError_t a4_commit(const A4Args &a, void *plan_fwd, void *plan_inv, hipStream_t s);
+
 // The incremental peak search: rescan the stale tiles, then reduce the tile
 // keys into the peak key; and every tile stale.
 hipError_t launch_peak_tiles(const Params &p, int ntiles, hipStream_t s);

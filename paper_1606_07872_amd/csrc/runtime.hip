@@ -41,8 +41,8 @@ struct asp_ctx {
     bool timing = false;
     std::vector<hipEvent_t> events;       // 2 per launch slot
     std::vector<int> ev_kind;             // kind of each recorded pair
-    double t_ms[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int64_t t_n[7] = {0, 0, 0, 0, 0, 0, 0};
+    double t_ms[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t t_n[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     // the proposal network (input-major layout) and training-sample recording
     float *net = nullptr;
     asp::NetParams netp{};
@@ -65,6 +65,14 @@ struct asp_ctx {
     hipfftHandle rf_fwd = 0, rf_inv = 0;
     bool rf_ready = false;
     asp::RefreshArgs rf{};
+    // the Asp-Clean2004 iteration: four padded grids and spectra, partial
+    // sums, the LM state and its pinned mirror, batched plans (first use)
+    double *a4_grid = nullptr, *a4_part = nullptr;
+    double2 *a4_spec = nullptr;
+    asp::A4State *a4_state = nullptr, *a4_host = nullptr;
+    hipfftHandle a4_fwd = 0, a4_inv = 0;
+    bool a4_ready = false;
+    asp::A4Args a4{};
     bool in_batch = false;                // a field of an asp_batch
     std::string err;
 };
@@ -113,6 +121,11 @@ void release(asp_ctx *c)
     if (c->rf_inv) (void)hipfftDestroy(c->rf_inv);
     (void)hipFree(c->dirty0); (void)hipFree(c->rf_grid); (void)hipFree(c->rf_spec);
     (void)hipFree(c->rf_pspec);
+    if (c->a4_fwd) (void)hipfftDestroy(c->a4_fwd);
+    if (c->a4_inv) (void)hipfftDestroy(c->a4_inv);
+    (void)hipFree(c->a4_grid); (void)hipFree(c->a4_part); (void)hipFree(c->a4_spec);
+    (void)hipFree(c->a4_state);
+    if (c->a4_host) (void)hipHostFree(c->a4_host);
     if (c->st_host) (void)hipHostFree(c->st_host);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -567,6 +580,133 @@ asp_status enqueue_iteration(asp_ctx *c)
     return s;
 }
 
+
+// Buffers and batched plans of the Asp-Clean2004 iteration (first use); the
+// PSF's spectrum, its peak pixel and the single plans are the refresh's.
+asp_status setup_2004(asp_ctx *c)
+{
+    if (c->a4_ready) return ASP_OK;
+    asp_status s = setup_refresh(c);
+    if (s == ASP_OK) s = setup_smoothing(c);
+    if (s != ASP_OK) return s;
+    const asp::RefreshArgs &r = c->rf;
+    const int64_t Py = r.Py, Px = r.Px;
+    const size_t plane = (size_t)(Py * Px), nspec = (size_t)Py * (size_t)(Px / 2 + 1);
+    hipError_t e = dev_alloc(&c->a4_grid, 4 * plane);
+    if (e == hipSuccess) e = dev_alloc(&c->a4_spec, 4 * nspec);
+    if (e == hipSuccess) e = dev_alloc(&c->a4_part, (size_t)asp::kA4Blocks * asp::kA4Sums);
+    if (e == hipSuccess) e = dev_alloc(&c->a4_state, 1);
+    if (e == hipSuccess && !c->a4_host) e = hipHostMalloc((void **)&c->a4_host, sizeof(asp::A4State));
+    if (e != hipSuccess)
+        return fail(c, e == hipErrorOutOfMemory ? ASP_ERR_NOMEM : ASP_ERR_DEVICE,
+                    std::string("Asp-Clean2004 buffers: ") + hipGetErrorString(e));
+    HIP_OR_FAIL(c, hipMemsetAsync(c->a4_state, 0, sizeof(asp::A4State), c->stream));
+    int n[2] = {(int)Py, (int)Px};
+    hipfftResult fr = hipfftPlanMany(&c->a4_fwd, 2, n, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_D2Z, 4);
+    if (fr == HIPFFT_SUCCESS)
+        fr = hipfftPlanMany(&c->a4_inv, 2, n, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, 4);
+    if (fr == HIPFFT_SUCCESS) fr = hipfftSetStream(c->a4_fwd, c->stream);
+    if (fr == HIPFFT_SUCCESS) fr = hipfftSetStream(c->a4_inv, c->stream);
+    if (fr != HIPFFT_SUCCESS)
+        return fail(c, ASP_ERR_DEVICE, std::string("Asp-Clean2004 plans: ") + fft_text(fr));
+    asp::A4Args &a = c->a4;
+    a.R = c->R;
+    a.st = c->st;
+    a.s = c->a4_state;
+    a.ca = c->ca; a.cx = c->cx; a.cy = c->cy; a.cs = c->cs;
+    a.c_added = c->c_added; a.c_updated = c->c_updated;
+    a.cap = c->cap;
+    a.grid = c->a4_grid;
+    a.spec = c->a4_spec;
+    a.pspec = r.pspec;
+    a.partials = c->a4_part;
+    a.H = c->H; a.W = c->W; a.Py = Py; a.Px = Px;
+    a.ci = r.ci; a.cj = r.cj;
+    a.budget = c->opt.lm_max_iter;
+    a.gain = c->P.gain;
+    a.window_sigmas = c->opt.window_sigmas;
+    const double wb = c->st_host->omega_b;
+    double smax = c->opt.max_width > 0.0 ? c->opt.max_width : (double)(c->H < c->W ? c->H : c->W) / 8.0;
+    a.s_max = smax > wb ? smax : wb;
+    a.mu0 = c->opt.lm_mu0;
+    a.tol = c->opt.lm_tol;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->a4_ready = true;
+    return ASP_OK;
+}
+
+asp_status pull_a4(asp_ctx *c)
+{
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->a4_host, c->a4_state, sizeof(asp::A4State),
+                                  hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return ASP_OK;
+}
+
+// One Asp-Clean2004 iteration: the peak and the stop test, the smoothing
+// start, LM evaluations of Eq. 3 until the fit ends (the host reads the
+// device's LM state after each), the exact update and the new component.
+asp_status step_2004(asp_ctx *c, asp_fit2004_report *rep)
+{
+    asp_status s = setup_2004(c);
+    if (s == ASP_OK) s = pull_all(c);
+    if (s != ASP_OK) return s;
+    s = stop_status(c);
+    if (s != ASP_OK) return s;
+    s = timed(c, 0, [&] {
+        return c->pk_tiles ? asp::launch_peak_tiles(c->P, c->pk_tiles, c->stream)
+                           : asp::launch_peak(c->P, c->peak_grid, c->stream);
+    });
+    if (s == ASP_OK) HIP_OR_FAIL(c, asp::launch_peak_decode(c->P, c->stream));
+    if (s == ASP_OK) s = timed(c, 4, [&] { return asp::launch_smooth_passes(c->P, 1, c->stream); });
+    if (s == ASP_OK) s = timed(c, 5, [&] { return asp::launch_smooth_pick(c->P, 1, c->stream); });
+    if (s == ASP_OK) HIP_OR_FAIL(c, asp::a4_begin(c->a4, c->stream));
+    if (s == ASP_OK) s = pull_all(c);
+    if (s == ASP_OK) s = pull_a4(c);
+    if (s != ASP_OK) return s;
+    const DevState *h = c->st_host;
+    if (h->stop) {
+        s = harvest(c);
+        return s != ASP_OK ? s : stop_status(c);
+    }
+    // every evaluation either ends the fit or spends a trial of the budget
+    for (int32_t n = 0; !c->a4_host->done; ++n) {
+        if (n > c->a4.budget + 1)
+            return fail(c, ASP_ERR_STATE, "the Asp-Clean2004 fit did not end within its budget");
+        s = timed(c, 7, [&] { return asp::a4_trial(c->a4, &c->a4_fwd, &c->a4_inv, c->stream); });
+        if (s == ASP_OK) s = pull_a4(c);
+        if (s != ASP_OK) return s;
+    }
+    s = timed(c, 8, [&] { return asp::a4_commit(c->a4, &c->rf_fwd, &c->rf_inv, c->stream); });
+    if (s != ASP_OK) return s;
+    if (c->pk_tiles) HIP_OR_FAIL(c, asp::launch_peak_mark_all(c->P, c->stream));
+    HIP_OR_FAIL(c, asp::launch_smooth_mark_all(c->P, c->stream));
+    s = pull_all(c);
+    if (s == ASP_OK) s = harvest(c);
+    if (s != ASP_OK) return s;
+    const asp::A4State *a = c->a4_host;
+    if (rep) {
+        memset(rep, 0, sizeof *rep);
+        rep->idx = h->idx;
+        rep->peak = h->peak;
+        rep->trials = a->trials;
+        rep->converged = a->converged;
+        rep->evaluations = a->evals;
+        for (int i = 0; i < 4; ++i) {
+            rep->start[i] = h->smooth_start[i];
+            rep->theta0[i] = a->theta0[i];
+            rep->theta[i] = a->theta[i];
+            rep->lo[i] = a->lo[i];
+            rep->hi[i] = a->hi[i];
+        }
+        rep->chi2_init = a->chi2_init;
+        rep->chi2_final = a->chi2;
+        rep->scale = h->smooth_scale;
+    }
+    s = stop_status(c);
+    if (s != ASP_OK) return s;
+    return a->converged ? ASP_OK : ASP_LM_NOT_CONVERGED;
+}
 }  // namespace
 
 extern "C" {
@@ -888,13 +1028,13 @@ asp_status asp_kernel_timing(asp_ctx *c, int32_t on)
         if (s != ASP_OK) return s;
     }
     c->timing = on != 0;
-    for (int i = 0; i < 7; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
+    for (int i = 0; i < 9; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
     return ASP_OK;
 }
 
 asp_status asp_kernel_times(asp_ctx *c, double *ms, int64_t *launches, int32_t n)
 {
-    if (!c || n < 0 || n > 7 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
+    if (!c || n < 0 || n > 9 || (n > 0 && (!ms || !launches))) return ASP_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i) { ms[i] = c->t_ms[i]; launches[i] = c->t_n[i]; }
     return ASP_OK;
 }
@@ -994,6 +1134,47 @@ asp_status asp_refresh_residual(asp_ctx *c)
     if (s == ASP_OK) s = pull_all(c);
     if (s == ASP_OK) s = harvest(c);
     return s;
+}
+
+asp_status asp_step_2004(asp_ctx *c, asp_fit2004_report *rep)
+{
+    if (!c) return ASP_ERR_INVALID_ARG;
+    if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_step_2004 inside a step-API sequence");
+    if (c->in_batch)
+        return fail(c, ASP_ERR_STATE, "the Asp-Clean2004 iteration is not available to batched fields");
+    return step_2004(c, rep);
+}
+
+asp_status asp_run_2004(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
+{
+    if (!c || n_iter < 0) return ASP_ERR_INVALID_ARG;
+    if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_run_2004 inside a step-API sequence");
+    if (c->in_batch)
+        return fail(c, ASP_ERR_STATE, "the Asp-Clean2004 iteration is not available to batched fields");
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    const DevState *h = c->st_host;
+    const int64_t k0 = h->k;
+    const unsigned long long t0 = h->sum_trials, nc0 = h->not_converged, ep0 = h->sum_eval_px,
+                             sm0 = h->sum_smoothed, pk0 = h->pk_tiles_done;
+    asp_status result = stop_status(c);
+    for (int64_t i = 0; result == ASP_OK && i < n_iter; ++i) {
+        s = step_2004(c, nullptr);
+        if (s < 0) return s;
+        result = (s == ASP_LM_NOT_CONVERGED) ? ASP_OK : s;
+    }
+    if (rep) {
+        memset(rep, 0, sizeof *rep);
+        rep->iterations = h->k - k0;
+        rep->total_iterations = h->k;
+        rep->components = h->L;
+        rep->lm_trials = (int64_t)(h->sum_trials - t0);
+        rep->not_converged = (int64_t)(h->not_converged - nc0);
+        rep->pixels_evaluated = (int64_t)(h->sum_eval_px - ep0);
+        rep->smoothed = (int64_t)(h->sum_smoothed - sm0);
+        rep->peak_tiles_scanned = (int64_t)(h->pk_tiles_done - pk0);
+    }
+    return result;
 }
 
 asp_status asp_smooth_work(asp_ctx *c, int64_t *pixels, double *flops)

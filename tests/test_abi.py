@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def header_symbols():
     text = open(os.path.join(ROOT, "include", "asp.h")).read()
-    return sorted(set(re.findall(r"\b(asp_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(asp_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
@@ -46,7 +46,7 @@ def test_struct_layouts_match_header(tmp_path):
     """sizeof/offsetof from the C header (compiled by gcc) vs the ctypes mirrors."""
     structs = {"asp_options": asp.Options, "asp_component": asp.Component,
                "asp_fit_report": asp.FitReport, "asp_run_report": asp.RunReport,
-               "asp_gauss": asp.Gauss}
+               "asp_gauss": asp.Gauss, "asp_fit2004_report": asp.Fit2004Report}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "asp.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
