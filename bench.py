@@ -293,6 +293,131 @@ def refresh_leg(args, f, rep, secs, ctx_plain, torch, asp):
     return out
 
 
+def fft_size(n: int) -> int:
+    """The smallest size >= n whose prime factors are 2, 3, 5 and 7 (the padded
+    grid of the library's FFT convolutions)."""
+    m = max(n, 1)
+    while True:
+        r = m
+        for p in (2, 3, 5, 7):
+            while r % p == 0:
+                r //= p
+        if r == 1:
+            return m
+        m += 1
+
+
+def eval2004_bytes(H, W, Py, Px):
+    """Least HBM bytes of one Asp-Clean2004 evaluation if each transform were a
+    single read-and-write pass: four FP64 grids cleared, transformed (D2Z),
+    multiplied by the PSF's spectrum, transformed back (Z2D), and the image
+    part of the four results read with R for the sums."""
+    P = float(Py * Px)
+    return 32 * P + 64 * P + 72 * P + 64 * P + 36.0 * H * W
+
+
+def asp2004_leg(args, f, rep, secs, torch, asp):
+    """The paper's comparison (Table 3): Asp-Clean2004 -- Eq. 3 fitted with the
+    true PSF, an FFT convolution in every evaluation -- against Asp-Clean2016,
+    both on the GPU.  On this field: the one-iteration time from iteration 0
+    of each; on a 256^2 field with loop gain 0.35 (the size and gain of
+    Table 3): both run to the same stop, then the ratios of total runtime,
+    one-iteration runtime and iteration count (2004 over 2016)."""
+    import numpy as np
+    H, W = f.shape
+    n = args.iters_2004
+    out = {}
+    # the 2004 iteration takes the smoothing method's matched-filter (L2) norm:
+    # with peak-1 beams, and no switch back to the residual's peak, it keeps
+    # choosing the widest trial width
+    ctx4 = asp.Context(f.dirty, f.psf, f.gain, f.threshold, max_iter=f.max_iter,
+                       max_active=f.max_active, smooth_norm=1)
+    ctx4.run_2004(1)                         # buffers, plans and the PSF spectrum
+    ctx4.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, r4 = ctx4.run_2004(n)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter() - t0
+    kt = ctx4.kernel_times()
+    ev_ms, ev_n = kt["eval2004"]
+    up_ms, up_n = kt["update2004"]
+    ctx4.close()
+    ctx6 = asp.Context(f.dirty, f.psf, f.gain, f.threshold, max_iter=f.max_iter,
+                       max_active=f.max_active)
+    ctx6.run(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc6, r6 = ctx6.run(n)
+    torch.cuda.synchronize()
+    t6 = time.perf_counter() - t0
+    ctx6.close()
+    Py = fft_size(H + f.psf.shape[0] - 1)
+    Px = fft_size(W + f.psf.shape[1] - 1)
+    eb = eval2004_bytes(H, W, Py, Px)
+    ev_s = ev_ms / ev_n * 1e-3 if ev_n else None
+    it4, it6 = r4["iterations"], r6["iterations"]
+    out["headline_field"] = {
+        "iterations": it4, "from_iteration": 1,
+        "ms_per_iteration_2004": 1e3 * t4 / max(it4, 1),
+        "ms_per_iteration_2016_same_iterations": 1e3 * t6 / max(it6, 1),
+        "ms_per_iteration_2016_timed_region": 1e3 * secs / max(rep["iterations"], 1),
+        "one_iteration_ratio": (t4 / max(it4, 1)) / (t6 / max(it6, 1)) if it6 and t6 > 0 else None,
+        "evaluations_per_fit": (r4["pixels_evaluated"] / (H * W)) / max(it4, 1),
+        "trials_per_fit_2004": r4["lm_trials"] / max(it4, 1),
+        "trials_per_fit_2016": r6["lm_trials"] / max(it6, 1),
+        "padded_grid": [Py, Px],
+        "evaluation": {"kernels": "render + batched D2Z + spectrum product + batched Z2D + sums + LM",
+                       "bound": "hbm", "ms": ev_s * 1e3 if ev_s else None,
+                       "bytes": eb, "achieved_gbs": eb / ev_s / 1e9 if ev_s else None,
+                       "frac": eb / ev_s / 1e9 / PEAK_HBM_GBS if ev_s else None,
+                       "share_of_iteration": ev_ms / (t4 * 1e3) if t4 > 0 else None},
+        "update_ms": up_ms / up_n if up_n else None}
+    log(f"2004 on {f.name}: {json.dumps(out['headline_field'])}")
+
+    import skygen
+    g = skygen.make_evla(256, 256, 60, 6, 16.0, args.max_iter_2004, 5, psf_crop=128)
+    gain = 0.35
+    thr = float(0.02 * np.abs(g.dirty).max())
+    # rocFFT compiles its kernels for a new size at first use (seconds): a
+    # throwaway context takes that cost before either algorithm is timed
+    w = asp.Context(g.dirty, g.psf, gain, thr, max_iter=2, smooth_norm=1)
+    w.run_2004(1)
+    w.run(1)
+    w.close()
+    res = {}
+    for name in ("2004", "2016"):
+        # Asp-Clean2016 with its start-value heuristic (the smoothing method
+        # and the 5 % switch); the 2004 iteration always smooths; both with
+        # the matched-filter (L2) norm of the smoothed images
+        c = asp.Context(g.dirty, g.psf, gain, thr, max_iter=args.max_iter_2004, max_active=5,
+                        init_mode=0 if name == "2004" else 2, smooth_norm=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, r = c.run_2004(args.max_iter_2004) if name == "2004" else c.run(args.max_iter_2004)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rms_minor = c.residual_rms()
+        c.refresh_residual()
+        res[name] = {"iterations": r["iterations"], "seconds": t,
+                     "stop": {0: "iteration cap", 1: "threshold", 2: "max_iter"}.get(rc, str(rc)),
+                     "ms_per_iteration": 1e3 * t / max(r["iterations"], 1),
+                     "trials_per_fit": r["lm_trials"] / max(r["iterations"], 1),
+                     "rms_minor_cycle": rms_minor, "rms_true": c.residual_rms()}
+        c.close()
+    a, b = res["2004"], res["2016"]
+    out["table3_style"] = {
+        "field": "256x256 EVLA-like (60 points, 6 Gaussians), gain 0.35, "
+                 f"threshold {thr:.4g} (2 % of the dirty peak), at most {args.max_iter_2004} "
+                 "iterations, smoothing with the L2 norm",
+        "asp2004": a, "asp2016": b,
+        "total_runtime_ratio": a["seconds"] / b["seconds"] if b["seconds"] > 0 else None,
+        "one_iteration_runtime_ratio": a["ms_per_iteration"] / b["ms_per_iteration"],
+        "iteration_number_ratio": a["iterations"] / max(b["iterations"], 1)}
+    log(f"2004 vs 2016, Table 3 style: {json.dumps(out['table3_style'])}")
+    return out
+
+
 def bench_batch(args):
     """64 independent fields of sizes in {256, 512, 1024, 2048}^2, each with its
     own Gaussian PSF: aggregate iterations/s of one graph-captured persistent
@@ -384,6 +509,12 @@ def main():
                     help="skip the incremental peak search leg")
     ap.add_argument("--no-refresh", action="store_true",
                     help="skip the exact-PSF refresh leg")
+    ap.add_argument("--no-2004", action="store_true",
+                    help="skip the Asp-Clean2004 comparison leg")
+    ap.add_argument("--iters-2004", type=int, default=6,
+                    help="Asp-Clean2004 iterations timed on the bench field")
+    ap.add_argument("--max-iter-2004", type=int, default=1000,
+                    help="iteration cap of the Table 3 style comparison (256^2 field)")
     ap.add_argument("--probe", type=int, default=5,
                     help="iterations per field of each autotuner probe (batch workload)")
     args = ap.parse_args()
@@ -498,6 +629,10 @@ def main():
     if not args.no_refresh:
         refresh = refresh_leg(args, f, rep, secs, ctx, torch, asp)
 
+    asp2004 = None
+    if not args.no_2004:
+        asp2004 = asp2004_leg(args, f, rep, secs, torch, asp)
+
     cpu = None
     if want_cpu:
         log(f"oracle baseline for {args.cpu_seconds:.0f}s from iteration {k0}")
@@ -527,6 +662,7 @@ def main():
         "smoothing": smoothing,
         "peak_tiles": peak_tiles,
         "refresh": refresh,
+        "asp2004_vs_2016": asp2004,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -346,7 +346,8 @@ asp_status asp_refresh_residual(asp_ctx *ctx);
  *      deconvolution is (gain F, omega), so asp_components and
  *      asp_refresh_residual read it like any other.
  * Earlier components are not refitted.  The host reads the device's LM state
- * after each evaluation.  The first call allocates four FP64 grids and their
+ * after each evaluation (after every four on padded grids of at most 1024^2
+ * pixels, where evaluations queued past the end of the fit return at once).  The first call allocates four FP64 grids and their
  * spectra of the refresh's padded size and batched FFT plans.  Must not be
  * inside a find_peak / fit / update sequence (ASP_ERR_STATE); not available
  * to batched fields.  Returns ASP_OK, ASP_LM_NOT_CONVERGED (budget used),
@@ -477,7 +478,8 @@ asp_status asp_batch_autotune(asp_batch *batch, int64_t probe_iter, int32_t *tea
  * passes (column and row pass together), 5 the smoothing pick, 6 the
  * exact-PSF refresh (rendering, two FFTs, spectral product, subtraction),
  * 7 one evaluation of the Asp-Clean2004 objective (rendering of the component
- * and its derivatives, the batched FFTs, the sums, the LM decision), 8 the
+ * and its derivatives, the batched FFTs, the sums, the LM decision; queued
+ * evaluations past the end of a fit included), 8 the
  * Asp-Clean2004 update (rendering, two FFTs, subtraction, the new component).
  * Switching timing on or off clears the totals. */
 asp_status asp_kernel_timing(asp_ctx *ctx, int32_t on);

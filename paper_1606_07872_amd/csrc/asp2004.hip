@@ -167,54 +167,64 @@ __global__ __launch_bounds__(kT) void k_a4_render(A4Args a, int final_img)
 __global__ __launch_bounds__(kT) void k_a4_mul(A4Args a, int images, int final_only)
 {
     if (final_only ? !finished(a) : !live(a)) return;
-    const int64_t m = a.Py * (a.Px / 2 + 1), n = (int64_t)images * m;
+    const int64_t m = a.Py * (a.Px / 2 + 1);
     const double scale = 1.0 / ((double)a.Py * (double)a.Px);
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-        const double2 v = a.spec[i], b = a.pspec[i % m];
-        a.spec[i] = make_double2((v.x * b.x - v.y * b.y) * scale, (v.x * b.y + v.y * b.x) * scale);
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT) {
+        const double2 b = a.pspec[i];
+        for (int img = 0; img < images; ++img) {
+            const double2 v = a.spec[img * m + i];
+            a.spec[img * m + i] =
+                make_double2((v.x * b.x - v.y * b.y) * scale, (v.x * b.y + v.y * b.x) * scale);
+        }
     }
 }
 
 // Per work-group partial sums over the image of the Gram matrix of
-// J = (B(*)g, F B(*)g_x, F B(*)g_y, F B(*)g_w), of J^T r with r = R - F B(*)g,
+// J = (B(*)g, F B(*)g_x, F B(*)g_y, F B(*)g_v), of J^T r with r = R - F B(*)g,
 // of m (m - 2 R) and of r^2.  Pixel (r, c) of the convolution sits at
-// (r + ci, c + cj) of the full linear convolution.
+// (r + ci, c + cj) of the full linear convolution.  Work-group b takes rows
+// b, b + nblk, ...; the sums are reduced in a fixed order (wave butterflies,
+// then the waves in order).
 __global__ __launch_bounds__(kT) void k_a4_gram(A4Args a)
 {
     if (!live(a)) return;
-    __shared__ double red[kT];
+    __shared__ double red[kT / 64][kA4Sums];
     const double F = a.s->te[0];
-    const int64_t plane = a.Py * a.Px, n = a.H * a.W;
+    const int64_t plane = a.Py * a.Px;
     double acc[kA4Sums];
 #pragma unroll
     for (int k = 0; k < kA4Sums; ++k) acc[k] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-        const int64_t r = i / a.W, c = i % a.W;
-        const int64_t o = (r + a.ci) * a.Px + (c + a.cj);
-        const double v0 = a.grid[o];
-        const double J[4] = {v0, F * a.grid[plane + o], F * a.grid[2 * plane + o],
-                             F * a.grid[3 * plane + o]};
-        const double D = (double)a.R[i];
-        const double m = F * v0, res = D - m;
-        int e = 0;
+    for (int64_t r = blockIdx.x; r < a.H; r += gridDim.x) {
+        const double *g0 = a.grid + (r + a.ci) * a.Px + a.cj;
+        const float *Rr = a.R + r * a.W;
+        for (int64_t c = threadIdx.x; c < a.W; c += kT) {
+            const double v0 = g0[c];
+            const double J[4] = {v0, F * g0[plane + c], F * g0[2 * plane + c], F * g0[3 * plane + c]};
+            const double D = (double)Rr[c];
+            const double m = F * v0, res = D - m;
+            int e = 0;
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
+            for (int p = 0; p < 4; ++p)
 #pragma unroll
-            for (int q = p; q < 4; ++q) acc[e++] += J[p] * J[q];
+                for (int q = p; q < 4; ++q) acc[e++] += J[p] * J[q];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) acc[10 + p] += J[p] * res;
-        acc[14] += m * (m - 2.0 * D);
-        acc[15] += res * res;
-    }
-    for (int k = 0; k < kA4Sums; ++k) {
-        red[threadIdx.x] = acc[k];
-        __syncthreads();
-        for (int h = kT / 2; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-            __syncthreads();
+            for (int p = 0; p < 4; ++p) acc[10 + p] += J[p] * res;
+            acc[14] += m * (m - 2.0 * D);
+            acc[15] += res * res;
         }
-        if (threadIdx.x == 0) a.partials[(int64_t)blockIdx.x * kA4Sums + k] = red[0];
-        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kA4Sums; ++k) {
+        double v = acc[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[w][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kA4Sums) {
+        double v = 0.0;
+        for (int q = 0; q < kT / 64; ++q) v += red[q][threadIdx.x];
+        a.partials[(int64_t)blockIdx.x * kA4Sums + threadIdx.x] = v;
     }
 }
 
@@ -303,11 +313,21 @@ __device__ void propose(const A4Args &a, A4State *s)
 __global__ __launch_bounds__(kT) void k_a4_lm(A4Args a)
 {
     if (!live(a)) return;
+    // thread t adds column t % 16 of rows t / 16, t / 16 + 16, ...; then the
+    // 16 row groups are added in order
+    __shared__ double grp[kT / kA4Sums][kA4Sums];
     __shared__ double tot[kA4Sums];
     const int t = threadIdx.x;
+    {
+        const int k = t % kA4Sums, g0 = t / kA4Sums;
+        double v = 0.0;
+        for (int b = g0; b < a.nblk; b += kT / kA4Sums) v += a.partials[(int64_t)b * kA4Sums + k];
+        grp[g0][k] = v;
+    }
+    __syncthreads();
     if (t < kA4Sums) {
         double v = 0.0;
-        for (int b = 0; b < kA4Blocks; ++b) v += a.partials[(int64_t)b * kA4Sums + t];
+        for (int q = 0; q < kT / kA4Sums; ++q) v += grp[q][t];
         tot[t] = v;
     }
     __syncthreads();
@@ -413,10 +433,10 @@ __global__ __launch_bounds__(kT) void k_a4_update(A4Args a)
 {
     if (!finished(a)) return;
     const double gF = a.gain * a.s->theta[0];
-    const int64_t n = a.H * a.W;
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-        const int64_t r = i / a.W, c = i % a.W;
-        a.R[i] = (float)((double)a.R[i] - gF * a.grid[(r + a.ci) * a.Px + (c + a.cj)]);
+    for (int64_t r = blockIdx.x; r < a.H; r += gridDim.x) {
+        const double *g0 = a.grid + (r + a.ci) * a.Px + a.cj;
+        float *Rr = a.R + r * a.W;
+        for (int64_t c = threadIdx.x; c < a.W; c += kT) Rr[c] = (float)((double)Rr[c] - gF * g0[c]);
     }
 }
 
@@ -487,7 +507,7 @@ hipError_t a4_trial(const A4Args &a, void *plan_fwd4, void *plan_inv4, hipStream
     if (e != hipSuccess) return e;
     e = fft_status(hipfftExecZ2D(*(hipfftHandle *)plan_inv4, (hipfftDoubleComplex *)a.spec, a.grid));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_a4_gram, dim3(kA4Blocks), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL(k_a4_gram, dim3(a.nblk), dim3(kT), 0, s, a);
     hipLaunchKernelGGL(k_a4_lm, dim3(1), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
@@ -505,7 +525,7 @@ hipError_t a4_commit(const A4Args &a, void *plan_fwd, void *plan_inv, hipStream_
     if (e != hipSuccess) return e;
     e = fft_status(hipfftExecZ2D(*(hipfftHandle *)plan_inv, (hipfftDoubleComplex *)a.spec, a.grid));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_a4_update, dim3(2048), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL(k_a4_update, dim3(a.nblk), dim3(kT), 0, s, a);
     hipLaunchKernelGGL(k_a4_append, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
 }

@@ -304,10 +304,11 @@ struct A4Args {
     double *grid;                  // 4 images Py x Px: g, dg/dx, dg/dy, dg/d(omega^2)
     double2 *spec;                 // their half spectra, Py x (Px/2 + 1) each
     const double2 *pspec;          // the PSF's
-    double *partials;              // kA4Blocks x kA4Sums
+    double *partials;              // nblk x kA4Sums
     int64_t H, W, Py, Px;
     int32_t ci, cj;                // the PSF's peak pixel
-    int32_t budget, pad;
+    int32_t budget;
+    int32_t nblk;                  // work-groups of the sums: min(kA4Blocks, H)
     double gain, window_sigmas, s_max, mu0, tol;
 };
 // Stop test after the peak, the start from the smoothing method, bounds.

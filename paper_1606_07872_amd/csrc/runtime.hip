@@ -623,6 +623,7 @@ asp_status setup_2004(asp_ctx *c)
     a.H = c->H; a.W = c->W; a.Py = Py; a.Px = Px;
     a.ci = r.ci; a.cj = r.cj;
     a.budget = c->opt.lm_max_iter;
+    a.nblk = (int32_t)(c->H < asp::kA4Blocks ? c->H : asp::kA4Blocks);
     a.gain = c->P.gain;
     a.window_sigmas = c->opt.window_sigmas;
     const double wb = c->st_host->omega_b;
@@ -669,12 +670,20 @@ asp_status step_2004(asp_ctx *c, asp_fit2004_report *rep)
         s = harvest(c);
         return s != ASP_OK ? s : stop_status(c);
     }
-    // every evaluation either ends the fit or spends a trial of the budget
-    for (int32_t n = 0; !c->a4_host->done; ++n) {
-        if (n > c->a4.budget + 1)
+    // Every evaluation either ends the fit or spends a trial of the budget, so
+    // at most budget + 1 are needed.  On small grids, where an evaluation
+    // costs less than the host's round trip, four are queued between reads of
+    // the LM state; those queued after the end return at once (their FFTs
+    // transform the stale grids, which the update clears).
+    const int per_read = c->rf.Py * c->rf.Px <= (int64_t)1024 * 1024 ? 4 : 1;
+    for (int32_t queued = 0; !c->a4_host->done;) {
+        if (queued >= c->a4.budget + 1)
             return fail(c, ASP_ERR_STATE, "the Asp-Clean2004 fit did not end within its budget");
-        s = timed(c, 7, [&] { return asp::a4_trial(c->a4, &c->a4_fwd, &c->a4_inv, c->stream); });
-        if (s == ASP_OK) s = pull_a4(c);
+        for (int b = 0; b < per_read && queued < c->a4.budget + 1; ++b, ++queued) {
+            s = timed(c, 7, [&] { return asp::a4_trial(c->a4, &c->a4_fwd, &c->a4_inv, c->stream); });
+            if (s != ASP_OK) return s;
+        }
+        s = pull_a4(c);
         if (s != ASP_OK) return s;
     }
     s = timed(c, 8, [&] { return asp::a4_commit(c->a4, &c->rf_fwd, &c->rf_inv, c->stream); });
