@@ -515,11 +515,13 @@ asp_status setup_refresh(asp_ctx *c)
         if (ph[i] > ph[best]) best = i;
     const int64_t Py = fft_size(H + Hp - 1), Px = fft_size(W + Wp - 1);
     const size_t nspec = (size_t)Py * (size_t)(Px / 2 + 1);
-    HIP_OR_FAIL(c, dev_alloc(&c->rf_grid, (size_t)(Py * Px)));
-    HIP_OR_FAIL(c, dev_alloc(&c->rf_spec, nspec));
-    HIP_OR_FAIL(c, dev_alloc(&c->rf_pspec, nspec));
-    hipfftResult r = hipfftPlan2d(&c->rf_fwd, (int)Py, (int)Px, HIPFFT_D2Z);
-    if (r == HIPFFT_SUCCESS) r = hipfftPlan2d(&c->rf_inv, (int)Py, (int)Px, HIPFFT_Z2D);
+    // a call after a failed one keeps what that one allocated
+    if (!c->rf_grid) HIP_OR_FAIL(c, dev_alloc(&c->rf_grid, (size_t)(Py * Px)));
+    if (!c->rf_spec) HIP_OR_FAIL(c, dev_alloc(&c->rf_spec, nspec));
+    if (!c->rf_pspec) HIP_OR_FAIL(c, dev_alloc(&c->rf_pspec, nspec));
+    hipfftResult r = HIPFFT_SUCCESS;
+    if (!c->rf_fwd) r = hipfftPlan2d(&c->rf_fwd, (int)Py, (int)Px, HIPFFT_D2Z);
+    if (r == HIPFFT_SUCCESS && !c->rf_inv) r = hipfftPlan2d(&c->rf_inv, (int)Py, (int)Px, HIPFFT_Z2D);
     if (r == HIPFFT_SUCCESS) r = hipfftSetStream(c->rf_fwd, c->stream);
     if (r == HIPFFT_SUCCESS) r = hipfftSetStream(c->rf_inv, c->stream);
     if (r != HIPFFT_SUCCESS) return fail(c, ASP_ERR_DEVICE, std::string("refresh plans: ") + fft_text(r));
@@ -592,18 +594,23 @@ asp_status setup_2004(asp_ctx *c)
     const asp::RefreshArgs &r = c->rf;
     const int64_t Py = r.Py, Px = r.Px;
     const size_t plane = (size_t)(Py * Px), nspec = (size_t)Py * (size_t)(Px / 2 + 1);
-    hipError_t e = dev_alloc(&c->a4_grid, 4 * plane);
-    if (e == hipSuccess) e = dev_alloc(&c->a4_spec, 4 * nspec);
-    if (e == hipSuccess) e = dev_alloc(&c->a4_part, (size_t)asp::kA4Blocks * asp::kA4Sums);
-    if (e == hipSuccess) e = dev_alloc(&c->a4_state, 1);
+    // a call after a failed one keeps what that one allocated
+    hipError_t e = hipSuccess;
+    if (!c->a4_grid) e = dev_alloc(&c->a4_grid, 4 * plane);
+    if (e == hipSuccess && !c->a4_spec) e = dev_alloc(&c->a4_spec, 4 * nspec);
+    if (e == hipSuccess && !c->a4_part)
+        e = dev_alloc(&c->a4_part, (size_t)asp::kA4Blocks * asp::kA4Sums);
+    if (e == hipSuccess && !c->a4_state) e = dev_alloc(&c->a4_state, 1);
     if (e == hipSuccess && !c->a4_host) e = hipHostMalloc((void **)&c->a4_host, sizeof(asp::A4State));
     if (e != hipSuccess)
         return fail(c, e == hipErrorOutOfMemory ? ASP_ERR_NOMEM : ASP_ERR_DEVICE,
                     std::string("Asp-Clean2004 buffers: ") + hipGetErrorString(e));
     HIP_OR_FAIL(c, hipMemsetAsync(c->a4_state, 0, sizeof(asp::A4State), c->stream));
     int n[2] = {(int)Py, (int)Px};
-    hipfftResult fr = hipfftPlanMany(&c->a4_fwd, 2, n, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_D2Z, 4);
-    if (fr == HIPFFT_SUCCESS)
+    hipfftResult fr = HIPFFT_SUCCESS;
+    if (!c->a4_fwd)
+        fr = hipfftPlanMany(&c->a4_fwd, 2, n, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_D2Z, 4);
+    if (fr == HIPFFT_SUCCESS && !c->a4_inv)
         fr = hipfftPlanMany(&c->a4_inv, 2, n, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, 4);
     if (fr == HIPFFT_SUCCESS) fr = hipfftSetStream(c->a4_fwd, c->stream);
     if (fr == HIPFFT_SUCCESS) fr = hipfftSetStream(c->a4_inv, c->stream);

@@ -216,3 +216,53 @@ def test_c4096_two_iterations():
         assert abs(np.sqrt(np.mean(got ** 2)) - np.sqrt(np.mean((R0 - conv) ** 2))) <= \
             1e-6 * np.sqrt(np.mean(got ** 2))
     ctx.close()
+
+
+def update_ok(ctx, R0, psf, gain, th, D):
+    ab, wb = ctx.psf_gauss()
+    conv = a4.Problem(R0, psf, wb).convolved([gain * th[0], th[1], th[2], th[3]])
+    got = ctx.residual().astype(np.float64)
+    tol = 2.0 ** -23 * np.maximum(np.abs(R0), np.abs(conv)) + 1e-9 * np.abs(D).max()
+    return bool(np.all(np.abs(got - (R0 - conv)) <= tol))
+
+
+def test_edge_cases():
+    """Images smaller than the PSF and than the interpolation taps, a budget of
+    one trial (against the oracle's), a negative source, and a full list."""
+    psf = skygen.gaussian_psf(9, 2.5).astype(np.float32)
+    g03 = float(np.float32(0.3))
+    for shape in [(1, 1), (3, 5), (7, 1)]:
+        dirty = np.zeros(shape, np.float32)
+        dirty[shape[0] // 2, shape[1] // 2] = 1.0
+        print("shape", shape, flush=True)
+        ctx = asp.Context(dirty, psf, 0.3, 0.0, max_iter=5)
+        R0 = ctx.residual().astype(np.float64)
+        rc, rep = ctx.step_2004()
+        assert rc in (asp.ASP_OK, asp.ASP_LM_NOT_CONVERGED), shape
+        assert update_ok(ctx, R0, psf, g03, rep["theta"], dirty), shape
+        ctx.close()
+    f = skygen.make_evla(128, 7, 40, 4, 10.0, 200, 1, psf_crop=128)
+    g = float(np.float32(f.gain))
+    ctx = asp.Context(f.dirty, f.psf, f.gain, 0.0, max_iter=5, lm_max_iter=1, smooth_norm=1)
+    ab, wb = ctx.psf_gauss()
+    rc, rep = ctx.step_2004()
+    assert rc in (asp.ASP_OK, asp.ASP_LM_NOT_CONVERGED) and rep["trials"] == 1
+    orc = a4.Oracle2004(f.dirty, f.psf, ab, wb, gain=g, lm_max_iter=1, smooth_norm="l2")
+    orep = orc.step(start=rep["start"])
+    assert orep["trials"] == 1 and bool(orep["converged"]) == bool(rep["converged"])
+    s = math.sqrt(orep["theta"][3] + wb * wb)
+    assert np.abs(rep["theta"] - orep["theta"]).max() <= 1e-6 * max(abs(orep["theta"][0]), s * s)
+    ctx.close()
+    # every source negative: the flux keeps the start's sign
+    ctx = asp.Context(-f.dirty, f.psf, f.gain, 0.0, max_iter=5)
+    R0 = ctx.residual().astype(np.float64)
+    rc, rep = ctx.step_2004()
+    assert rep["theta"][0] < 0.0 and rep["hi"][0] == 0.0 and rep["lo"][0] == -np.inf
+    assert update_ok(ctx, R0, f.psf, g, rep["theta"], f.dirty)
+    ctx.close()
+    # a list of one component
+    ctx = asp.Context(f.dirty, f.psf, f.gain, 0.0, max_iter=5, capacity=1)
+    ctx.step_2004()
+    with pytest.raises(asp.AspError):
+        ctx.step_2004()
+    ctx.close()
