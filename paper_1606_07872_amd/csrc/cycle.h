@@ -112,31 +112,53 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
     __syncthreads();
     const int nr = nr_s;
     const int32_t br0 = bb_s[0], br1 = bb_s[1], bc0 = bb_s[2], bc1 = bb_s[3];
-    const int ntx = (bc1 - bc0 + 64) / 64, nty = (br1 - br0 + 4) / 4;
+    // tiles of 64 columns x kUpdRows rows; a thread takes column lc of rows
+    // lr, lr + 4, ...: its kUpdRows / 4 pixels are loaded together, so that a
+    // wave keeps several loads in flight
+    constexpr int kUpdRows = 16, kPer = kUpdRows / 4;
+    const int ntx = (bc1 - bc0 + 64) / 64, nty = (br1 - br0 + kUpdRows) / kUpdRows;
     const int64_t ntiles = (int64_t)ntx * nty;
     unsigned long long cnt = 0;
     const int lr = t >> 6, lc = t & 63;
     for (int64_t tile = rank; tile < ntiles; tile += size) {
-        const int32_t tr0 = br0 + (int32_t)(tile / ntx) * 4;
+        const int32_t tr0 = br0 + (int32_t)(tile / ntx) * kUpdRows;
         const int32_t tc0 = bc0 + (int32_t)(tile % ntx) * 64;
         bool any = false;
         for (int i = 0; i < nr; ++i)
-            any |= (rb[i][0] <= tr0 + 3 && tr0 <= rb[i][1] && rb[i][2] <= tc0 + 63 && tc0 <= rb[i][3]);
+            any |= (rb[i][0] <= tr0 + kUpdRows - 1 && tr0 <= rb[i][1] && rb[i][2] <= tc0 + 63 &&
+                    tc0 <= rb[i][3]);
         if (!any) continue;
-        const int32_t r = tr0 + lr, c = tc0 + lc;
-        if (r > br1 || c > bc1) continue;
-        float acc = 0.0f;
-        bool hit = false;
-        for (int i = 0; i < nr; ++i) {
-            if (r < rb[i][0] || r > rb[i][1] || c < rb[i][2] || c > rb[i][3]) continue;
-            float dx = (float)(c - rcx[i]) - rfx[i];
-            float dy = (float)(r - rcy[i]) - rfy[i];
-            acc += ramp[i] * __expf(-(dx * dx + dy * dy) * rinv[i]);
-            hit = true;
+        const int32_t c = tc0 + lc;
+        if (c > bc1) continue;
+        float acc[kPer], val[kPer];
+        bool hit[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int32_t r = tr0 + lr + 4 * k;
+            acc[k] = 0.0f;
+            hit[k] = false;
+            if (r > br1) continue;
+            for (int i = 0; i < nr; ++i)
+                hit[k] |= !(r < rb[i][0] || r > rb[i][1] || c < rb[i][2] || c > rb[i][3]);
         }
-        if (hit) {
-            float *px = p.R + (int64_t)r * p.W + c;
-            *px = *px + acc;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            val[k] = hit[k] ? p.R[(int64_t)(tr0 + lr + 4 * k) * p.W + c] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (!hit[k]) continue;
+            const int32_t r = tr0 + lr + 4 * k;
+            for (int i = 0; i < nr; ++i) {
+                if (r < rb[i][0] || r > rb[i][1] || c < rb[i][2] || c > rb[i][3]) continue;
+                float dx = (float)(c - rcx[i]) - rfx[i];
+                float dy = (float)(r - rcy[i]) - rfy[i];
+                acc[k] += ramp[i] * __expf(-(dx * dx + dy * dy) * rinv[i]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (!hit[k]) continue;
+            p.R[(int64_t)(tr0 + lr + 4 * k) * p.W + c] = val[k] + acc[k];
             ++cnt;
         }
     }
