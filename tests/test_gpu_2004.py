@@ -266,3 +266,26 @@ def test_edge_cases():
     with pytest.raises(asp.AspError):
         ctx.step_2004()
     ctx.close()
+
+
+def test_components_and_timers_after_2004_steps():
+    """asp_components reads a 2004 component back as (gain F, omega) by Eqs. 5-6,
+    and the kernel timers count its evaluations and updates."""
+    f = skygen.make_evla(128, 7, 40, 4, 10.0, 200, 1, psf_crop=128)
+    ctx = asp.Context(f.dirty, f.psf, f.gain, 0.0, max_iter=50)
+    ctx.kernel_timing(True)
+    reps = [ctx.step_2004()[1] for _ in range(3)]
+    kt = ctx.kernel_times()
+    assert kt["update2004"][1] == 3
+    assert kt["eval2004"][1] >= sum(r["evaluations"] for r in reps)
+    assert kt["eval2004"][0] > 0.0
+    g = float(np.float32(f.gain))
+    comps = ctx.components()
+    assert len(comps) == 3
+    for r, c in zip(reps, comps):
+        th = r["theta"]
+        assert c["flux"] == pytest.approx(g * th[0], rel=1e-12)
+        assert (c["x"], c["y"]) == (th[1], th[2])
+        if not c["is_point"]:
+            assert c["width"] == pytest.approx(math.sqrt(th[3]), rel=1e-9)
+    ctx.close()
