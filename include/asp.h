@@ -247,6 +247,43 @@ asp_status asp_residual_device(asp_ctx *ctx, float **dev);
 /* The Gaussian fitted to the PSF main lobe (Sect. 3: alpha_b, omega_b). */
 asp_status asp_psf_gauss(asp_ctx *ctx, double *alpha_b, double *omega_b);
 
+/*
+ * The model image of Sect. 2 step 2, I_model = sum of the components in the sky
+ * plane (Eqs. 5-6), rendered as asp_refresh_residual renders it: a component
+ * at least 1 px wide as its Gaussian sampled on the window of half-width
+ * max(3, ceil(c_w omega)); a narrower one, points included, per axis by
+ * three Gauss-Hermite nodes spread with the Lanczos-3 kernel and normalised.
+ * Rendered in FP64 on the device; out receives H*W FP32 values (host buffer,
+ * row-major).  The first call allocates the refresh's buffers and an H x W
+ * device image.  Not available to batched fields.
+ */
+asp_status asp_model_image(asp_ctx *ctx, float *out);
+
+/*
+ * Checkpoint and resume.  The state is the residual, the component list, the
+ * iteration count, the smoothing method's switch and the PSF's Gaussian
+ * (alpha_b, omega_b): everything the next iteration depends on.  The options
+ * and the input images are not part of it: load a state into a context
+ * created from the same images, with the options the run should continue
+ * under.  A stop is not part of it either: after a load the next iteration
+ * applies the loading context's stop test.  Because every
+ * reduction on the path has a fixed order, iterations after a load repeat
+ * those of the run that saved the state, bit for bit.
+ *   asp_state_size  bytes of the state blob now (64 + 4 H W + 48 L).
+ *   asp_save_state  writes the blob into a host buffer of cap bytes; *bytes
+ *                   (nullable) receives its size; ASP_ERR_CAPACITY when cap
+ *                   is short.
+ *   asp_load_state  restores a blob: ASP_ERR_INVALID_ARG when it is not a
+ *                   state, has the wrong length, or comes from an image of
+ *                   another size or another PSF fit; ASP_ERR_CAPACITY when its
+ *                   list does not fit the context's capacity.
+ * Both refuse to run inside a find_peak / fit / update sequence
+ * (ASP_ERR_STATE); batched fields cannot load a state.
+ */
+asp_status asp_state_size(asp_ctx *ctx, int64_t *bytes);
+asp_status asp_save_state(asp_ctx *ctx, void *blob, int64_t cap, int64_t *bytes);
+asp_status asp_load_state(asp_ctx *ctx, const void *blob, int64_t bytes);
+
 /* Iterations done (k) and components (L). */
 asp_status asp_counts(asp_ctx *ctx, int64_t *k, int64_t *L);
 

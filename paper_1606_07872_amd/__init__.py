@@ -32,7 +32,8 @@ EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destro
            "asp_batch_last_error", "asp_batch_field", "asp_batch_config", "asp_batch_get_config",
            "asp_batch_run", "asp_batch_autotune", "asp_smooth_peak", "asp_smooth_map",
            "asp_smooth_widths", "asp_smooth_work", "asp_refresh_residual", "asp_step_2004",
-           "asp_run_2004"]
+           "asp_run_2004", "asp_model_image", "asp_state_size", "asp_save_state",
+           "asp_load_state"]
 
 MLP_PARAMS = 329220
 MLP_IN = 1024
@@ -176,6 +177,10 @@ def lib():
         L.asp_smooth_work.argtypes = [vp, P(i64), P(f64)]
         L.asp_refresh_residual.argtypes = [vp]
         L.asp_step_2004.argtypes = [vp, P(Fit2004Report)]
+        L.asp_model_image.argtypes = [vp, vp]
+        L.asp_state_size.argtypes = [vp, P(i64)]
+        L.asp_save_state.argtypes = [vp, vp, i64, P(i64)]
+        L.asp_load_state.argtypes = [vp, vp, i64]
         L.asp_run_2004.argtypes = [vp, i64, P(RunReport)]
         for name in EXPORTS:
             if name not in ("asp_destroy", "asp_last_error", "asp_mlp_destroy",
@@ -370,6 +375,24 @@ class Context:
     def refresh_residual(self):
         """Replace the residual by I_dirty - B (*) I_model with the true PSF."""
         self._check(lib().asp_refresh_residual(self._ctx))
+
+    def model_image(self) -> np.ndarray:
+        """I_model: the components rendered in the sky plane (H x W float32)."""
+        out = np.empty((self.H, self.W), dtype=np.float32)
+        self._check(lib().asp_model_image(self._ctx, out.ctypes.data))
+        return out
+
+    # -- checkpoint and resume -------------------------------------------------
+    def save_state(self) -> bytes:
+        n = ctypes.c_int64()
+        self._check(lib().asp_state_size(self._ctx, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(lib().asp_save_state(self._ctx, buf, n.value, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def load_state(self, blob: bytes):
+        b = ctypes.create_string_buffer(bytes(blob), len(blob))
+        self._check(lib().asp_load_state(self._ctx, b, len(blob)))
 
     # -- the Asp-Clean2004 comparison path -------------------------------------
     def step_2004(self):

@@ -275,6 +275,8 @@ struct RefreshArgs {
 };
 hipError_t refresh_psf_spectrum(const RefreshArgs &a, void *plan_fwd, hipStream_t s);
 hipError_t refresh_residual(const RefreshArgs &a, void *plan_fwd, void *plan_inv, hipStream_t s);
+// The model image (the refresh's rendering, no convolution) into out, H x W FP32.
+hipError_t render_model(const RefreshArgs &a, float *out, hipStream_t s);
 
 // The Asp-Clean2004 iteration (Sect. 2 steps 1-4 with the objective of
 // Eq. 3): Levenberg-Marquardt state of the one sky component (F, x, y,

@@ -211,6 +211,13 @@ __global__ __launch_bounds__(kT) void k_rf_finish(RefreshArgs a)
     }
 }
 
+// The image part of the rendered model, rounded to FP32.
+__global__ __launch_bounds__(kT) void k_rf_model_out(RefreshArgs a, float *out)
+{
+    for (int64_t r = blockIdx.x; r < a.H; r += gridDim.x)
+        for (int64_t c = threadIdx.x; c < a.W; c += kT) out[r * a.W + c] = (float)a.grid[r * a.Px + c];
+}
+
 hipError_t fft_error(hipfftResult r)
 {
     return r == HIPFFT_SUCCESS ? hipSuccess : hipErrorUnknown;
@@ -243,6 +250,16 @@ hipError_t refresh_residual(const RefreshArgs &a, void *plan_fwd, void *plan_inv
     e = fft_error(hipfftExecZ2D(*(hipfftHandle *)plan_inv, (hipfftDoubleComplex *)a.spec, a.grid));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rf_finish, dim3(2048), dim3(kT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t render_model(const RefreshArgs &a, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rf_zero, dim3(2048), dim3(kT), 0, s, a);
+    const int64_t tiles = ((a.H + 63) / 64) * ((a.W + 63) / 64);
+    hipLaunchKernelGGL(k_rf_render, dim3((unsigned)tiles), dim3(kT), 0, s, a);
+    const int64_t rows = a.H < 4096 ? a.H : 4096;
+    hipLaunchKernelGGL(k_rf_model_out, dim3((unsigned)rows), dim3(kT), 0, s, a, out);
     return hipGetLastError();
 }
 

@@ -73,6 +73,7 @@ struct asp_ctx {
     hipfftHandle a4_fwd = 0, a4_inv = 0;
     bool a4_ready = false;
     asp::A4Args a4{};
+    float *model_dev = nullptr;           // asp_model_image's device copy (first use)
     bool in_batch = false;                // a field of an asp_batch
     std::string err;
 };
@@ -126,6 +127,7 @@ void release(asp_ctx *c)
     (void)hipFree(c->a4_grid); (void)hipFree(c->a4_part); (void)hipFree(c->a4_spec);
     (void)hipFree(c->a4_state);
     if (c->a4_host) (void)hipHostFree(c->a4_host);
+    (void)hipFree(c->model_dev);
     if (c->st_host) (void)hipHostFree(c->st_host);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -723,6 +725,22 @@ asp_status step_2004(asp_ctx *c, asp_fit2004_report *rep)
     if (s != ASP_OK) return s;
     return a->converged ? ASP_OK : ASP_LM_NOT_CONVERGED;
 }
+
+// The checkpoint blob: this header, then R (H x W FP32), then the component
+// list (a, x, y, s as L doubles each, then iteration added and updated as L
+// int64 each), all in host byte order.
+struct StateHeader {
+    char magic[8];
+    int64_t H, W, k, L;
+    int32_t smooth_now, reserved;
+    double alpha_b, omega_b;
+};
+constexpr char kStateMagic[8] = {'A', 'S', 'P', 'S', 'T', 'A', 'T', '1'};
+
+int64_t state_bytes(int64_t H, int64_t W, int64_t L)
+{
+    return (int64_t)sizeof(StateHeader) + 4 * H * W + 48 * L;
+}
 }  // namespace
 
 extern "C" {
@@ -1244,6 +1262,117 @@ asp_status asp_record_count(asp_ctx *c, int64_t *n)
     asp_status s = pull_all(c);
     if (s != ASP_OK) return s;
     *n = c->st_host->rec_n;
+    return ASP_OK;
+}
+
+asp_status asp_model_image(asp_ctx *c, float *out)
+{
+    if (!c || !out) return ASP_ERR_INVALID_ARG;
+    if (c->in_batch) return fail(c, ASP_ERR_STATE, "the model image is not available to batched fields");
+    asp_status s = setup_refresh(c);
+    if (s != ASP_OK) return s;
+    if (!c->model_dev) HIP_OR_FAIL(c, dev_alloc(&c->model_dev, (size_t)(c->H * c->W)));
+    asp::RefreshArgs a = c->rf;
+    a.force = 1;
+    HIP_OR_FAIL(c, asp::render_model(a, c->model_dev, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(out, c->model_dev, sizeof(float) * c->H * c->W,
+                                  hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return ASP_OK;
+}
+
+asp_status asp_state_size(asp_ctx *c, int64_t *bytes)
+{
+    if (!c || !bytes) return ASP_ERR_INVALID_ARG;
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    *bytes = state_bytes(c->H, c->W, c->st_host->L);
+    return ASP_OK;
+}
+
+asp_status asp_save_state(asp_ctx *c, void *blob, int64_t cap, int64_t *bytes)
+{
+    if (!c || cap < 0 || (!blob && cap > 0)) return ASP_ERR_INVALID_ARG;
+    if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_save_state inside a step-API sequence");
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    const DevState *h = c->st_host;
+    const int64_t L = h->L, need = state_bytes(c->H, c->W, L);
+    if (bytes) *bytes = need;
+    if (cap < need) return fail(c, ASP_ERR_CAPACITY, "the state blob needs asp_state_size bytes");
+    StateHeader hd;
+    memset(&hd, 0, sizeof hd);
+    memcpy(hd.magic, kStateMagic, sizeof hd.magic);
+    hd.H = c->H; hd.W = c->W; hd.k = h->k; hd.L = L;
+    hd.smooth_now = h->smooth_now;
+    hd.alpha_b = h->alpha_b; hd.omega_b = h->omega_b;
+    char *p = (char *)blob;
+    memcpy(p, &hd, sizeof hd);
+    p += sizeof hd;
+    HIP_OR_FAIL(c, hipMemcpyAsync(p, c->R, sizeof(float) * c->H * c->W, hipMemcpyDeviceToHost,
+                                  c->stream));
+    p += sizeof(float) * c->H * c->W;
+    double *const lists[4] = {c->ca, c->cx, c->cy, c->cs};
+    for (double *d : lists) {
+        if (L) HIP_OR_FAIL(c, hipMemcpyAsync(p, d, sizeof(double) * L, hipMemcpyDeviceToHost, c->stream));
+        p += sizeof(double) * L;
+    }
+    int64_t *const iters[2] = {c->c_added, c->c_updated};
+    for (int64_t *d : iters) {
+        if (L) HIP_OR_FAIL(c, hipMemcpyAsync(p, d, sizeof(int64_t) * L, hipMemcpyDeviceToHost, c->stream));
+        p += sizeof(int64_t) * L;
+    }
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return ASP_OK;
+}
+
+asp_status asp_load_state(asp_ctx *c, const void *blob, int64_t bytes)
+{
+    if (!c || !blob || bytes < (int64_t)sizeof(StateHeader)) return ASP_ERR_INVALID_ARG;
+    if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_load_state inside a step-API sequence");
+    if (c->in_batch) return fail(c, ASP_ERR_STATE, "a batched field cannot load a state");
+    StateHeader hd;
+    memcpy(&hd, blob, sizeof hd);
+    if (memcmp(hd.magic, kStateMagic, sizeof hd.magic) != 0)
+        return fail(c, ASP_ERR_INVALID_ARG, "not an asp state blob");
+    if (hd.H != c->H || hd.W != c->W)
+        return fail(c, ASP_ERR_INVALID_ARG, "the state was saved from an image of another size");
+    if (hd.L < 0 || hd.k < 0 || bytes != state_bytes(hd.H, hd.W, hd.L))
+        return fail(c, ASP_ERR_INVALID_ARG, "the state blob has the wrong length");
+    if (hd.L > c->cap) return fail(c, ASP_ERR_CAPACITY, "the component list does not fit this context");
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    DevState *h = c->st_host;
+    if (hd.alpha_b != h->alpha_b || hd.omega_b != h->omega_b)
+        return fail(c, ASP_ERR_INVALID_ARG, "the state was saved with another PSF fit");
+    const char *p = (const char *)blob + sizeof hd;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->R, p, sizeof(float) * c->H * c->W, hipMemcpyHostToDevice,
+                                  c->stream));
+    p += sizeof(float) * c->H * c->W;
+    double *const lists[4] = {c->ca, c->cx, c->cy, c->cs};
+    for (double *d : lists) {
+        if (hd.L) HIP_OR_FAIL(c, hipMemcpyAsync(d, p, sizeof(double) * hd.L, hipMemcpyHostToDevice, c->stream));
+        p += sizeof(double) * hd.L;
+    }
+    int64_t *const iters[2] = {c->c_added, c->c_updated};
+    for (int64_t *d : iters) {
+        if (hd.L) HIP_OR_FAIL(c, hipMemcpyAsync(d, p, sizeof(int64_t) * hd.L, hipMemcpyHostToDevice, c->stream));
+        p += sizeof(int64_t) * hd.L;
+    }
+    h->k = hd.k;
+    h->L = hd.L;
+    h->stop = 0;                        // the loading context's options decide the next stop
+    h->smooth_now = hd.smooth_now;
+    h->smooth_ready = 0;
+    h->fit_ready = 0;
+    h->forced_idx = -1;
+    h->have_proposal = 0;
+    for (int i = 0; i < asp::kPeakSlots; ++i) h->peak_keys[i] = 0ull;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->st, h, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+    // the whole residual changed: every tile of the incremental searches is stale
+    if (c->pk_tiles) HIP_OR_FAIL(c, asp::launch_peak_mark_all(c->P, c->stream));
+    if (c->P.sm.n > 0) HIP_OR_FAIL(c, asp::launch_smooth_mark_all(c->P, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     return ASP_OK;
 }
 

@@ -95,3 +95,9 @@ def test_null_context_calls():
     assert L.asp_find_peak(None, None, None) == asp.ASP_ERR_INVALID_ARG
     assert L.asp_run(None, 1, None) == asp.ASP_ERR_INVALID_ARG
     assert L.asp_last_error(None) == b"null context"
+    assert L.asp_step_2004(None, None) == asp.ASP_ERR_INVALID_ARG
+    assert L.asp_run_2004(None, 1, None) == asp.ASP_ERR_INVALID_ARG
+    assert L.asp_model_image(None, None) == asp.ASP_ERR_INVALID_ARG
+    assert L.asp_state_size(None, None) == asp.ASP_ERR_INVALID_ARG
+    assert L.asp_save_state(None, None, 0, None) == asp.ASP_ERR_INVALID_ARG
+    assert L.asp_load_state(None, None, 0) == asp.ASP_ERR_INVALID_ARG
