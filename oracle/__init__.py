@@ -26,8 +26,17 @@ COMP_DTYPE = np.dtype([("a", "<f8"), ("x", "<f8"), ("y", "<f8"), ("s", "<f8"),
                        ("iter_added", "<i8"), ("iter_updated", "<i8")])
 
 
+# A build of the same source made elsewhere (the sanitizer test's
+# AddressSanitizer/UBSan build) can stand in for the library.
+_OVERRIDE = os.environ.get("ASP_ORACLE_LIB")
+if _OVERRIDE:
+    _SO = _OVERRIDE
+
+
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (FP64, -O2, no fast-math, no contraction)."""
+    if _OVERRIDE:
+        return _SO
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
