@@ -80,7 +80,7 @@ __device__ inline void peak_scan(const float *__restrict__ R, int64_t n, uint32_
 // ===========================================================================
 // Residual update: R += sum over the plan's rects of sign * G on the rect,
 // each pixel read and written once (Sect. 2 step 3 with the Gaussian beam).
-// Blocks stride over 64 x 4 tiles of the plan's bounding box and skip tiles
+// Blocks stride over 64 x 16 tiles of the plan's bounding box and skip tiles
 // that meet no rect.
 // ===========================================================================
 
