@@ -1,0 +1,67 @@
+"""Free-run parity: the HIP minor cycle and the FP64 oracle each run from the
+same dirty image with no resynchronisation.  Reported: the first iteration
+whose peak or active set differs (the GPU keeps R in FP32, the oracle in FP64,
+so near-ties eventually part the trajectories), the parameter errors of every
+fit before it, and the final residual RMS and model flux of both runs."""
+import numpy as np
+import pytest
+
+import oracle
+import skygen
+from parity import param_errors
+
+pytestmark = pytest.mark.gpu
+
+asp = pytest.importorskip("paper_1606_07872_amd")
+
+
+CASES = {
+    # name: (field, iterations, least iterations before the trajectories part)
+    "c128_s0": (lambda: skygen.make_c128(0), 200, 150),
+    "c128_s3": (lambda: skygen.make_c128(3), 200, 150),
+    "c1024": (lambda: skygen.make_c1024(1000), 300, 250),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_free_run_against_the_oracle(case):
+    make, n_iter, need = CASES[case]
+    f = make()
+    ctx = asp.Context(f.dirty, f.psf, f.gain, f.threshold, max_iter=n_iter,
+                      max_active=f.max_active)
+    ab, wb = ctx.psf_gauss()
+    g = float(np.float32(f.gain))
+    orc = oracle.Oracle(f.dirty, gain=g, threshold=float(np.float32(f.threshold)),
+                        max_iter=n_iter, max_active=f.max_active, alpha_b=ab, omega_b=wb)
+    gpu, cpu = [], []
+    for _ in range(n_iter):
+        rc, idx, _ = ctx.find_peak()
+        if rc != asp.ASP_OK:
+            break
+        _, rep = ctx.fit_active_set(idx)
+        ctx.update_residual()
+        gpu.append((idx, tuple(rep["members"]), np.asarray(rep["theta"]), rep["converged"]))
+    for _ in range(n_iter):
+        r = orc.step()
+        if r["status"] not in (oracle.ORC_OK, oracle.ORC_LM_NOT_CONVERGED):
+            break
+        cpu.append((r["idx"], tuple(r["members"]), r["theta"].ravel(), r["converged"]))
+    n = min(len(gpu), len(cpu))
+    first = next((i for i in range(n) if gpu[i][:2] != cpu[i][:2]), n)
+    for i in range(first):
+        if gpu[i][3] and cpu[i][3]:
+            assert param_errors(gpu[i][2], cpu[i][2]).max() <= 1.0, i
+    R = ctx.residual().astype(np.float64)
+    rms_g, rms_c = float(np.sqrt(np.mean(R ** 2))), float(np.sqrt(np.mean(orc.R ** 2)))
+    flux_g = float(sum(c["flux"] for c in ctx.components()))
+    flux_c = float(sum(c["flux"] for c in orc.components()))
+    print(f"{case}: iterations gpu {len(gpu)} oracle {len(cpu)}, first divergence at "
+          f"{first}, rms {rms_g:.6g} / {rms_c:.6g}, model flux {flux_g:.6g} / {flux_c:.6g}",
+          flush=True)
+    print(f"  relative differences: rms {abs(rms_g - rms_c) / rms_c:.3g}, "
+          f"flux {abs(flux_g - flux_c) / abs(flux_c):.3g}", flush=True)
+    assert first >= need
+    if first == n:
+        assert abs(rms_g - rms_c) <= 1e-4 * rms_c
+        assert abs(flux_g - flux_c) <= 1e-4 * abs(flux_c)
+    ctx.close()
