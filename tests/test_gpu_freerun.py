@@ -20,6 +20,7 @@ CASES = {
     "c128_s0": (lambda: skygen.make_c128(0), 200, 150),
     "c128_s3": (lambda: skygen.make_c128(3), 200, 150),
     "c1024": (lambda: skygen.make_c1024(1000), 300, 250),
+    "c4096": (lambda: skygen.make_c4096(4096), 100, 80),
 }
 
 
