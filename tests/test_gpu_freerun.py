@@ -66,3 +66,43 @@ def test_free_run_against_the_oracle(case):
         assert abs(rms_g - rms_c) <= 1e-4 * rms_c
         assert abs(flux_g - flux_c) <= 1e-4 * abs(flux_c)
     ctx.close()
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_free_run_with_the_smoothing_method(seed):
+    """Init mode 2 (the smoothing start and the 5 % switch) on both sides: the
+    smoothed images are FP32 on the GPU, so a near tie between two scales or
+    pixels can part the runs; the runs are compared up to that point and their
+    ends in residual RMS."""
+    f = skygen.make_c128(seed)
+    n_iter = 120
+    ctx = asp.Context(f.dirty, f.psf, f.gain, f.threshold, max_iter=n_iter,
+                      max_active=f.max_active, init_mode=2)
+    ab, wb = ctx.psf_gauss()
+    orc = oracle.Oracle(f.dirty, gain=float(np.float32(f.gain)),
+                        threshold=float(np.float32(f.threshold)), max_iter=n_iter,
+                        max_active=f.max_active, alpha_b=ab, omega_b=wb, smooth_scales=5)
+    gpu, cpu = [], []
+    for _ in range(n_iter):
+        rc, idx, _ = ctx.find_peak()
+        if rc != asp.ASP_OK:
+            break
+        _, rep = ctx.fit_active_set(idx)
+        ctx.update_residual()
+        gpu.append((idx, tuple(rep["members"]), rep["init_source"] == 3))
+    for _ in range(n_iter):
+        r = orc.step()
+        if r["status"] not in (oracle.ORC_OK, oracle.ORC_LM_NOT_CONVERGED):
+            break
+        cpu.append((r["idx"], tuple(r["members"]), bool(r["smoothed"])))
+    n = min(len(gpu), len(cpu))
+    first = next((i for i in range(n) if gpu[i] != cpu[i]), n)
+    R = ctx.residual().astype(np.float64)
+    rms_g, rms_c = float(np.sqrt(np.mean(R ** 2))), float(np.sqrt(np.mean(orc.R ** 2)))
+    smoothed = sum(1 for s in gpu[:first] if s[2])
+    print(f"smoothing seed {seed}: first divergence at {first} of {n} "
+          f"({smoothed} smoothed starts before it), rms {rms_g:.6g} / {rms_c:.6g}", flush=True)
+    assert first >= 100 and smoothed >= 50
+    if first == n:
+        assert abs(rms_g - rms_c) <= 1e-4 * rms_c
+    ctx.close()
