@@ -239,8 +239,23 @@ asp_status asp_components_raw(asp_ctx *ctx, double *out4, int64_t cap, int64_t *
 /* Copy the residual to a host buffer of H*W floats. */
 asp_status asp_residual(asp_ctx *ctx, float *out);
 /* Sum over the image of residual^2, in FP64 and a fixed order, on the
- * device (no copy of the image). */
+ * device (no copy of the image).  The full pass also re-bases the tracked
+ * sum below. */
 asp_status asp_residual_sumsq(asp_ctx *ctx, double *sum_sq);
+/* The same sum, tracked without a pass over the image (for a noise-level stop
+ * rule, Sect. 2 step 4): each windowed update (asp_update_residual, the steps
+ * of asp_step / asp_run and of a batch) adds, per work-group, the FP64 change
+ * sum(R_new^2 - R_old^2) over the pixels it rewrote into a slot of its own;
+ * a full pass re-bases it at create, after every exact-PSF refresh, every
+ * Asp-Clean2004 update, asp_load_state and asp_residual_sumsq.  The read adds
+ * the base and the slots in a fixed order: deterministic, equal to the full
+ * pass up to FP64 rounding; the error grows by about 2^-53 of the sum at the
+ * last re-base per update (the per-pixel change is the difference of two
+ * exact squares), so it is relative to that sum, not to the current one.  A
+ * caller that writes the residual through asp_residual_device calls
+ * asp_residual_sumsq afterwards to re-base.  *sum_sq (host) receives the sum;
+ * ASP_ERR_INVALID_ARG for a null argument. */
+asp_status asp_residual_sumsq_tracked(asp_ctx *ctx, double *sum_sq);
 /* Device pointer of the residual (valid until asp_destroy). */
 asp_status asp_residual_device(asp_ctx *ctx, float **dev);
 

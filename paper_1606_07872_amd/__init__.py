@@ -28,7 +28,7 @@ EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destro
            "asp_kernel_timing", "asp_kernel_times", "asp_set_mlp", "asp_set_init_mode",
            "asp_record", "asp_record_count", "asp_mlp_create", "asp_mlp_destroy",
            "asp_mlp_last_error", "asp_mlp_loss_grad", "asp_mlp_train", "asp_mlp_forward",
-           "asp_mlp_weights", "asp_residual_sumsq", "asp_batch_create", "asp_batch_destroy",
+           "asp_mlp_weights", "asp_residual_sumsq", "asp_residual_sumsq_tracked", "asp_batch_create", "asp_batch_destroy",
            "asp_batch_last_error", "asp_batch_field", "asp_batch_config", "asp_batch_get_config",
            "asp_batch_run", "asp_batch_autotune", "asp_smooth_peak", "asp_smooth_map",
            "asp_smooth_widths", "asp_smooth_work", "asp_refresh_residual", "asp_step_2004",
@@ -159,6 +159,7 @@ def lib():
         L.asp_mlp_forward.argtypes = [vp, vp, i64, vp]
         L.asp_mlp_weights.argtypes = [vp, vp]
         L.asp_residual_sumsq.argtypes = [vp, P(f64)]
+        L.asp_residual_sumsq_tracked.argtypes = [vp, P(f64)]
         i32 = ctypes.c_int32
         L.asp_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, P(Options), P(vp)]
         L.asp_batch_destroy.argtypes = [vp]
@@ -316,6 +317,15 @@ class Context:
         v = ctypes.c_double()
         self._check(lib().asp_residual_sumsq(self._ctx, ctypes.byref(v)))
         return float(np.sqrt(v.value / (self.H * self.W)))
+
+    def residual_sumsq(self, tracked: bool = False) -> float:
+        """Sum of residual^2 in FP64: a full pass (which also re-bases the
+        tracked sum), or with tracked=True the sum kept up to date by the
+        windowed updates, read without a pass over the image."""
+        v = ctypes.c_double()
+        f = lib().asp_residual_sumsq_tracked if tracked else lib().asp_residual_sumsq
+        self._check(f(self._ctx, ctypes.byref(v)))
+        return v.value
 
     def residual_device_ptr(self) -> int:
         p = ctypes.c_void_p()

@@ -93,7 +93,14 @@ struct DevState {
                                                    // (j) and row (8 + j) passes
     unsigned long long pk_tiles_done;   // tiles rescanned by the incremental peak search
     PeakTiles pk;                       // the incremental peak search's buffers
+    // the tracked sum of R^2: sq_base (a full pass at the last wholesale change
+    // of R) plus the windowed deltas of the updates since, one slot per update
+    // work-group index
+    double *sq_slots;
+    int32_t sq_nslots, sq_pad;
+    double sq_base;
 };
+constexpr int kSqSlots = 4096;
 
 // State of one fit shared by the work-groups of the fit kernel.  The
 // published part (m .. th_old) is written by one work-group and read by all
@@ -326,6 +333,10 @@ hipError_t a4_commit(const A4Args &a, void *plan_fwd, void *plan_inv, hipStream_
 hipError_t launch_peak_tiles(const Params &p, int ntiles, hipStream_t s);
 hipError_t launch_peak_mark_all(const Params &p, hipStream_t s);
 hipError_t launch_propose(const Params &p, const NetParams &net, int use_net, hipStream_t s);
+// The tracked sum of R^2: re-based on a full pass (*total) with the slots
+// cleared, and read (base plus the slots in a fixed order) into *out.
+hipError_t launch_sq_rebase(DevState *st, const double *total, hipStream_t s);
+hipError_t launch_sq_read(DevState *st, double *out, hipStream_t s);
 hipError_t launch_sumsq(const float *img, int64_t n, double *part, int nblk, double *out,
                         hipStream_t s);
 hipError_t fit_kernel_setup();

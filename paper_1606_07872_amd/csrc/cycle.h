@@ -92,6 +92,7 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
     __shared__ float rfx[kMaxRects], rfy[kMaxRects], ramp[kMaxRects], rinv[kMaxRects];
     __shared__ int32_t nr_s, bb_s[4];
     __shared__ unsigned long long cnt_s[4];
+    __shared__ double dsq_s[4];
     const int t = threadIdx.x;
     __syncthreads();
     if (t == 0) {
@@ -119,6 +120,7 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
     const int ntx = (bc1 - bc0 + 64) / 64, nty = (br1 - br0 + kUpdRows) / kUpdRows;
     const int64_t ntiles = (int64_t)ntx * nty;
     unsigned long long cnt = 0;
+    double dsq = 0.0;                   // change of the sum of R^2 over this thread's pixels
     const int lr = t >> 6, lc = t & 63;
     for (int64_t tile = rank; tile < ntiles; tile += size) {
         const int32_t tr0 = br0 + (int32_t)(tile / ntx) * kUpdRows;
@@ -158,7 +160,9 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             if (!hit[k]) continue;
-            p.R[(int64_t)(tr0 + lr + 4 * k) * p.W + c] = val[k] + acc[k];
+            const float nv = val[k] + acc[k];
+            p.R[(int64_t)(tr0 + lr + 4 * k) * p.W + c] = nv;
+            dsq += (double)nv * nv - (double)val[k] * val[k];
             ++cnt;
         }
     }
@@ -207,14 +211,24 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
             }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-    if ((t & 63) == 0) cnt_s[t >> 6] = cnt;
+    for (int off = 32; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off, 64);
+        dsq += __shfl_xor(dsq, off, 64);
+    }
+    if ((t & 63) == 0) {
+        cnt_s[t >> 6] = cnt;
+        dsq_s[t >> 6] = dsq;
+    }
     __syncthreads();
     if (t == 0) {
         unsigned long long c = cnt_s[0] + cnt_s[1] + cnt_s[2] + cnt_s[3];
         if (c) {
             atomicAdd(&st->update_px, c);
             atomicAdd(&st->sum_update_px, c);
+            // the work-group's own slot of the tracked sum of R^2: the same
+            // work-group index in every launch, so no two writers and a fixed order
+            if (st->sq_slots)
+                st->sq_slots[rank % st->sq_nslots] += ((dsq_s[0] + dsq_s[1]) + dsq_s[2]) + dsq_s[3];
         }
     }
 }

@@ -285,6 +285,39 @@ hipError_t launch_sumsq(const float *img, int64_t n, double *part, int nblk, dou
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_sq_rebase(DevState *st, const double *total)
+{
+    for (int i = threadIdx.x; i < st->sq_nslots; i += blockDim.x) st->sq_slots[i] = 0.0;
+    if (threadIdx.x == 0) st->sq_base = *total;
+}
+
+// base + slot sums: thread t adds slots t, t + 256, ...; then the 256 sums in order
+__global__ __launch_bounds__(256) void k_sq_read(DevState *st, double *out)
+{
+    __shared__ double red[256];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < st->sq_nslots; i += blockDim.x) v += st->sq_slots[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = st->sq_base;
+        for (int i = 0; i < 256; ++i) sum += red[i];
+        *out = sum;
+    }
+}
+
+hipError_t launch_sq_rebase(DevState *st, const double *total, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sq_rebase, dim3(1), dim3(256), 0, s, st, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_sq_read(DevState *st, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sq_read, dim3(1), dim3(256), 0, s, st, out);
+    return hipGetLastError();
+}
+
 // Eqs. 5-6: sky-plane parameters of every component.
 __global__ void k_components(Params p, asp_component *out)
 {

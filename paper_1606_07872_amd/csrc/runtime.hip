@@ -46,7 +46,8 @@ struct asp_ctx {
     // the proposal network (input-major layout) and training-sample recording
     float *net = nullptr;
     asp::NetParams netp{};
-    double *sumsq = nullptr;              // 1024 partials + the total
+    double *sumsq = nullptr;              // 1024 partials, the total, the tracked read
+    double *sq_slots = nullptr;           // per update work-group deltas of the sum of R^2
     // the smoothing method's device buffers (allocated on first use)
     float *sm_vt = nullptr, *sm_taps = nullptr, *sm_w = nullptr, *sm_map = nullptr;
     unsigned long long *sm_keys = nullptr;
@@ -114,6 +115,7 @@ void release(asp_ctx *c)
     (void)hipFree(c->st); (void)hipFree(c->work); (void)hipFree(c->comp_out);
     (void)hipFree(c->fg); (void)hipFree(c->partials); (void)hipFree(c->net);
     (void)hipFree(c->sumsq);
+    (void)hipFree(c->sq_slots);
     (void)hipFree(c->sm_vt); (void)hipFree(c->sm_taps); (void)hipFree(c->sm_w);
     (void)hipFree(c->sm_map); (void)hipFree(c->sm_keys); (void)hipFree(c->sm_dirty);
     (void)hipFree(c->sm_list); (void)hipFree(c->sm_count);
@@ -343,6 +345,8 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     CREATE_HIP(dev_alloc(&c->c_added, c->cap));
     CREATE_HIP(dev_alloc(&c->c_updated, c->cap));
     CREATE_HIP(dev_alloc(&c->st, 1));
+    CREATE_HIP(dev_alloc(&c->sumsq, 1026));
+    CREATE_HIP(dev_alloc(&c->sq_slots, asp::kSqSlots));
     CREATE_HIP(dev_alloc(&c->work, np > 2 ? np : 2));
     const int fit_grid = asp::fit_grid_size(c->device);
     CREATE_HIP(dev_alloc(&c->fg, 1));
@@ -357,6 +361,8 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     CREATE_HIP(hipMemcpyAsync(c->psf, psf, sizeof(float) * np, kp, c->stream));
     memset(c->st_host, 0, sizeof(DevState));
     c->st_host->forced_idx = -1;
+    c->st_host->sq_slots = c->sq_slots;
+    c->st_host->sq_nslots = asp::kSqSlots;
     CREATE_HIP(hipMemcpyAsync(c->st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice,
                               c->stream));
     // NaN / Inf in either image is an error (no CPU scan: a device kernel).
@@ -370,6 +376,9 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
         c->err = flags[0] ? "dirty image holds NaN or Inf" : "PSF holds NaN or Inf";
         return bail(ASP_ERR_NONFINITE);
     }
+    // the tracked sum of R^2 starts from a full pass over the dirty image
+    CREATE_HIP(asp::launch_sumsq(c->R, n, c->sumsq, 1024, c->sumsq + 1024, c->stream));
+    CREATE_HIP(asp::launch_sq_rebase(c->st, c->sumsq + 1024, c->stream));
     CREATE_HIP(asp::launch_psf_fit(c->psf, Hp, Wp, opt.psf_lobe_frac, c->st, c->work, c->stream));
     CREATE_HIP(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost,
                               c->stream));
@@ -385,7 +394,8 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     int64_t pg = cus * 8;
     int64_t need = (n4 + 255) / 256;
     c->peak_grid = (int)(need < pg ? (need > 0 ? need : 1) : pg);
-    c->update_grid = cus * 4;
+    // one slot of the tracked sum of R^2 per update work-group
+    c->update_grid = cus * 4 < asp::kSqSlots ? cus * 4 : asp::kSqSlots;
 
     Params &P = c->P;
     P.R = c->R; P.H = H; P.W = W;
@@ -547,8 +557,18 @@ asp_status setup_refresh(asp_ctx *c)
     return ASP_OK;
 }
 
+// A full pass over R re-bases the tracked sum of R^2 (after every change of R
+// that is not a windowed update).
+asp_status rebase_sumsq(asp_ctx *c)
+{
+    HIP_OR_FAIL(c, asp::launch_sumsq(c->R, c->H * c->W, c->sumsq, 1024, c->sumsq + 1024,
+                                     c->stream));
+    HIP_OR_FAIL(c, asp::launch_sq_rebase(c->st, c->sumsq + 1024, c->stream));
+    return ASP_OK;
+}
+
 // One refresh on the stream; then every tile of the incremental searches is
-// stale (the whole residual changed).
+// stale and the tracked sum of R^2 is re-based (the whole residual changed).
 asp_status enqueue_refresh(asp_ctx *c, int force)
 {
     asp::RefreshArgs a = c->rf;
@@ -559,7 +579,7 @@ asp_status enqueue_refresh(asp_ctx *c, int force)
     if (s != ASP_OK) return s;
     if (c->pk_tiles) HIP_OR_FAIL(c, asp::launch_peak_mark_all(c->P, c->stream));
     if (c->P.sm.n > 0) HIP_OR_FAIL(c, asp::launch_smooth_mark_all(c->P, c->stream));
-    return ASP_OK;
+    return rebase_sumsq(c);
 }
 
 asp_status enqueue_iteration(asp_ctx *c)
@@ -699,7 +719,8 @@ asp_status step_2004(asp_ctx *c, asp_fit2004_report *rep)
     if (s != ASP_OK) return s;
     if (c->pk_tiles) HIP_OR_FAIL(c, asp::launch_peak_mark_all(c->P, c->stream));
     HIP_OR_FAIL(c, asp::launch_smooth_mark_all(c->P, c->stream));
-    s = pull_all(c);
+    s = rebase_sumsq(c);
+    if (s == ASP_OK) s = pull_all(c);
     if (s == ASP_OK) s = harvest(c);
     if (s != ASP_OK) return s;
     const asp::A4State *a = c->a4_host;
@@ -1012,10 +1033,19 @@ asp_status asp_residual(asp_ctx *c, float *out)
 asp_status asp_residual_sumsq(asp_ctx *c, double *sum_sq)
 {
     if (!c || !sum_sq) return ASP_ERR_INVALID_ARG;
-    if (!c->sumsq) HIP_OR_FAIL(c, dev_alloc(&c->sumsq, 1025));
-    HIP_OR_FAIL(c, asp::launch_sumsq(c->R, c->H * c->W, c->sumsq, 1024, c->sumsq + 1024,
-                                     c->stream));
+    asp_status s = rebase_sumsq(c);
+    if (s != ASP_OK) return s;
     HIP_OR_FAIL(c, hipMemcpyAsync(sum_sq, c->sumsq + 1024, sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return ASP_OK;
+}
+
+asp_status asp_residual_sumsq_tracked(asp_ctx *c, double *sum_sq)
+{
+    if (!c || !sum_sq) return ASP_ERR_INVALID_ARG;
+    HIP_OR_FAIL(c, asp::launch_sq_read(c->st, c->sumsq + 1025, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(sum_sq, c->sumsq + 1025, sizeof(double), hipMemcpyDeviceToHost,
                                   c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     return ASP_OK;
@@ -1372,6 +1402,8 @@ asp_status asp_load_state(asp_ctx *c, const void *blob, int64_t bytes)
     // the whole residual changed: every tile of the incremental searches is stale
     if (c->pk_tiles) HIP_OR_FAIL(c, asp::launch_peak_mark_all(c->P, c->stream));
     if (c->P.sm.n > 0) HIP_OR_FAIL(c, asp::launch_smooth_mark_all(c->P, c->stream));
+    asp_status rs = rebase_sumsq(c);
+    if (rs != ASP_OK) return rs;
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     return ASP_OK;
 }

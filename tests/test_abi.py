@@ -101,3 +101,4 @@ def test_null_context_calls():
     assert L.asp_state_size(None, None) == asp.ASP_ERR_INVALID_ARG
     assert L.asp_save_state(None, None, 0, None) == asp.ASP_ERR_INVALID_ARG
     assert L.asp_load_state(None, None, 0) == asp.ASP_ERR_INVALID_ARG
+    assert L.asp_residual_sumsq_tracked(None, None) == asp.ASP_ERR_INVALID_ARG
