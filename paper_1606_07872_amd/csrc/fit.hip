@@ -448,8 +448,9 @@ __device__ __forceinline__ void evaluate_tiles(const Params &p, WGShared &S, flo
         if (ti >= ntiles || lin >= total) return;
         int w = 0;
         while (lin >= S.pref[w + 1]) ++w;
-        const int64_t local = lin - S.pref[w];
-        const int32_t wc = S.win[w][3] - S.win[w][2] + 1;
+        // a window lies inside the image (fewer than 2^32 pixels): 32-bit division
+        const uint32_t local = (uint32_t)(lin - S.pref[w]);
+        const uint32_t wc = (uint32_t)(S.win[w][3] - S.win[w][2] + 1);
         r = S.win[w][0] + (int32_t)(local / wc);
         c = S.win[w][2] + (int32_t)(local % wc);
         valid = true;
@@ -502,11 +503,23 @@ __device__ __forceinline__ void evaluate_tiles(const Params &p, WGShared &S, flo
         for (int u = 0; u < kOwnMax; ++u) {
             if (u >= n_own) break;
             const int ci = oi[u], ck = ok_[u];
-            float ts = 0.0f;
-            for (int q = my_s; q < kT; q += S_sub) {
-                const float *rq = tile + q * kTileStride;
-                ts += rq[ci] * rq[ck];
+            // four interleaved chains (pixels q, q + S_sub, ... in turn), added
+            // in a fixed order: a quarter of the dependent adds per tile
+            float ts0 = 0.0f, ts1 = 0.0f, ts2 = 0.0f, ts3 = 0.0f;
+            int q = my_s;
+            for (; q + 3 * S_sub < kT; q += 4 * S_sub) {
+                const float *r0 = tile + q * kTileStride, *r1 = r0 + S_sub * kTileStride;
+                const float *r2 = r1 + S_sub * kTileStride, *r3 = r2 + S_sub * kTileStride;
+                ts0 += r0[ci] * r0[ck];
+                ts1 += r1[ci] * r1[ck];
+                ts2 += r2[ci] * r2[ck];
+                ts3 += r3[ci] * r3[ck];
             }
+            for (; q < kT; q += S_sub) {
+                const float *rq = tile + q * kTileStride;
+                ts0 += rq[ci] * rq[ck];
+            }
+            const float ts = (ts0 + ts1) + (ts2 + ts3);
             const float y = ts - acc_c[u];
             const float tt = acc_s[u] + y;
             acc_c[u] = (tt - acc_s[u]) - y;
@@ -568,10 +581,11 @@ __device__ __forceinline__ void evaluate_tiles_reg(const Params &p, WGShared &S,
         const int64_t lin = ti * kT + t;
         if (lin >= total) continue;
         const int w = (M > 1 && lin >= S.pref[1]) ? 1 : 0;
-        const int32_t local = (int32_t)(lin - S.pref[w]);
-        const int32_t wc = S.win[w][3] - S.win[w][2] + 1;
-        const int32_t r = S.win[w][0] + local / wc;
-        const int32_t c = S.win[w][2] + local % wc;
+        // a window lies inside the image (fewer than 2^32 pixels): 32-bit division
+        const uint32_t local = (uint32_t)(lin - S.pref[w]);
+        const uint32_t wc = (uint32_t)(S.win[w][3] - S.win[w][2] + 1);
+        const int32_t r = S.win[w][0] + (int32_t)(local / wc);
+        const int32_t c = S.win[w][2] + (int32_t)(local % wc);
         if (M > 1 && w == 1 && in_box(S.win[0], r, c)) continue;
         npx += 1.0;
         double D = (double)p.R[(int64_t)r * p.W + c];
