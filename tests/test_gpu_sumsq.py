@@ -109,3 +109,18 @@ def test_tracked_sum_in_a_batch():
     for i in range(len(fields)):
         check(b.field(i), f"batch field {i}", dirty_sumsq(fields[i]))
     b.close()
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (3, 5), (7, 1), (1, 9)])
+def test_tracked_sum_on_degenerate_shapes(shape):
+    """Images smaller than a window: every update window is clipped."""
+    H, W = shape
+    dirty = np.zeros(shape, np.float32)
+    dirty[H // 2, W // 2] = 1.0
+    if H * W > 1:
+        dirty.flat[0] = -0.3
+    psf = skygen.gaussian_psf(33, 3.0).astype(np.float32)
+    ctx = asp.Context(dirty, psf, 0.3, 0.0, max_iter=6)
+    ctx.run(6)
+    check(ctx, f"shape {shape}", float(np.sum(dirty.astype(np.float64) ** 2)))
+    ctx.close()
