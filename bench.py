@@ -13,8 +13,10 @@ Besides the throughput the line carries:
                 is the FP32 Gram accumulation, (n+1)(n+2) flops per pixel
                 evaluation, against the FP32 vector peak
   hbm           achieved HBM rates of the peak search (4 H W bytes per
-                launch) and of the residual update (8 bytes per pixel
-                read-modify-written)
+                launch) and, with --update-launch 1, of the residual update
+                (8 bytes per pixel read-modify-written); by default the
+                update runs at the end of the fit kernel and is part of its
+                launch time
   cpu_baseline  the FP64 oracle, single-threaded, continuing the same run
                 from the state at the start of the timed region for a bounded
                 number of seconds
@@ -504,6 +506,9 @@ def main():
     ap.add_argument("--solo-tiles", type=int, default=0)
     ap.add_argument("--min-tiles", type=int, default=0)
     ap.add_argument("--group", type=int, default=0, help="work-groups per arrival counter")
+    ap.add_argument("--update-launch", type=int, default=0, choices=(0, 1),
+                    help="1: the residual update in its own launch instead of at the end "
+                         "of the fit kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--no-learned", action="store_true",
@@ -559,7 +564,8 @@ def main():
     total = args.warmup + args.steps
     ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=max(f.max_iter, total),
                       max_active=f.max_active, fit_solo_tiles=args.solo_tiles,
-                      fit_min_tiles=args.min_tiles, fit_group=args.group)
+                      fit_min_tiles=args.min_tiles, fit_group=args.group,
+                      update_launch=args.update_launch)
     del d_dirty, d_psf
     torch.cuda.synchronize()
     ctx.run(args.warmup)
@@ -604,6 +610,7 @@ def main():
                         "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": tr,
                         "avg_launch_us": avg_s * 1e6, "launches": fit_n,
                         "work_per_launch": flops_per_launch,
+                        "includes_update": not args.update_launch,
                         "share_of_step": fit_ms / (secs * 1e3)}
         hbm = {}
         if peak_n and peak_ms > 0:
@@ -616,6 +623,9 @@ def main():
             gbs = b / (upd_ms / upd_n * 1e-3) / 1e9
             hbm["k_update"] = {"achieved_gbs": gbs, "frac": gbs / PEAK_HBM_GBS,
                                "avg_launch_us": upd_ms / upd_n * 1e3, "bytes_per_launch": b}
+        elif not args.update_launch:
+            hbm["k_update"] = {"fused_into": "k_fit",
+                               "bytes_per_iteration": 8.0 * rep["pixels_updated"] / max(done, 1)}
 
     rms_plain = ctx.residual_rms()
     learned = None

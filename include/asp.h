@@ -133,6 +133,12 @@ typedef struct {
     int32_t refresh_every;       /* > 0: asp_run replaces the residual by the
                                     exact one (asp_refresh_residual) after every
                                     refresh_every-th iteration; 0 = never        */
+    int32_t update_launch;       /* 0: in asp_run the residual update (Sect. 2
+                                    step 3) runs at the end of the fit kernel,
+                                    on all its work-groups (default); 1: its own
+                                    kernel launch, as asp_update_residual does.
+                                    Same result either way                       */
+    int32_t reserved;            /* 0                                            */
     double window_sigmas;        /* window half-width factor c_w; default 5      */
     double max_width;            /* upper bound on s; 0 = max(omega_b, min(H,W)/8) */
     double lm_mu0;               /* initial damping; default 1e-3                */

@@ -54,6 +54,7 @@ class Options(ctypes.Structure):
                 ("fit_group", ctypes.c_int32), ("smooth_scales", ctypes.c_int32),
                 ("smooth_norm", ctypes.c_int32), ("switch_area", ctypes.c_int32),
                 ("peak_tiles", ctypes.c_int32), ("refresh_every", ctypes.c_int32),
+                ("update_launch", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("window_sigmas", ctypes.c_double), ("max_width", ctypes.c_double),
                 ("lm_mu0", ctypes.c_double), ("lm_tol", ctypes.c_double),
                 ("psf_lobe_frac", ctypes.c_double), ("stream", ctypes.c_void_p)]

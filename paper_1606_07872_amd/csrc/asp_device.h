@@ -160,7 +160,7 @@ struct Params {
     int32_t min_tiles;             // least tiles per work-group in a shared trial
     unsigned long long spin_ticks; // time bound of every wait between work-groups
     int32_t group;                 // work-groups per first-level arrival counter
-    int32_t pad_g;
+    int32_t fuse_update;           // k_fit ends with the residual update on all its work-groups
     FitGlobal *fg;
     double *partials;              // fit_grid x kPartStride
     // recording of (patch, target) training pairs; rec_cap = 0 disables

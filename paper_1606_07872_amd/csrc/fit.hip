@@ -82,6 +82,7 @@ struct WGShared {
     unsigned long long tmark;      // phase timer mark (thread 0)
     unsigned int gen;
     int32_t last, abort, done, ok, finished, accept, stop;
+    int32_t upd;                   // the fit committed and this launch also updates R
 };
 
 // Phase timers of the driving work-group (thread 0): the mark lives in LDS so
@@ -1283,7 +1284,16 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
                 S.cmd = ld_shared(&G->m);
             }
             __syncthreads();
-            if (S.done) return;
+            if (S.done) {
+                if (S.done == 2) {
+                    // the committed plan was written by work-group 0 with plain
+                    // stores: acquire before reading it
+                    if (t == 0) acquire_fence();
+                    __syncthreads();
+                    update_tiles(p, wg, nwg);
+                }
+                return;
+            }
             prepare(p, S, S.cmd, G->th_e, G->th_old, true);
             const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
             const int geff = eval_groups(ntiles, nwg, p.min_tiles);
@@ -1308,10 +1318,17 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
     }
     __syncthreads();
     if (!S.stop) {
-        fit_trials(p, G, S, tile, red, A, H2, nwg, 0);
-        if (t == 0) G->done = 1;
+        const bool committed = fit_trials(p, G, S, tile, red, A, H2, nwg, 0);
+        // with fuse_update every work-group takes its tiles of the update
+        // (Sect. 2 step 3) after this publication; the end of the kernel is
+        // the barrier before the next iteration reads R
+        if (t == 0) {
+            S.upd = committed && p.fuse_update ? 1 : 0;
+            G->done = S.upd ? 2 : 1;
+        }
     }
     publish(G);
+    if (!S.stop && S.upd) update_tiles(p, 0, nwg);
 }
 
 // ===========================================================================

@@ -297,7 +297,8 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
         opt.lm_max_iter < 1 || opt.init_mode < 0 || opt.init_mode > 2 || opt.capacity < 0 ||
         opt.smooth_scales < 0 || opt.smooth_scales > ASP_MAX_SCALES || opt.smooth_norm < 0 ||
         opt.smooth_norm > 1 || opt.switch_area < 0 || opt.switch_area > 1 || opt.peak_tiles < 0 ||
-        opt.peak_tiles > 1 || opt.refresh_every < 0 ||
+        opt.peak_tiles > 1 || opt.refresh_every < 0 || opt.update_launch < 0 ||
+        opt.update_launch > 1 || opt.reserved != 0 ||
         opt.fit_solo_tiles < -1 || opt.fit_min_tiles < 0 || opt.fit_group < 0 ||
         !(opt.window_sigmas > 0.0) || !(opt.max_width >= 0.0) || !(opt.lm_mu0 > 0.0) ||
         !(opt.lm_tol > 0.0) || !(opt.psf_lobe_frac > 0.0 && opt.psf_lobe_frac < 1.0))
@@ -598,8 +599,12 @@ asp_status enqueue_iteration(asp_ctx *c)
         s = timed(c, 3, [&] {
             return asp::launch_propose(c->P, c->netp, use_net(c) ? 1 : 0, c->stream);
         });
-    if (s == ASP_OK) s = timed(c, 1, [&] { return asp::launch_fit(c->P, c->stream); });
-    if (s == ASP_OK)
+    // the fit kernel's work-groups take the update after the commit, unless
+    // the options ask for its own launch
+    asp::Params q = c->P;
+    q.fuse_update = c->opt.update_launch == 0 ? 1 : 0;
+    if (s == ASP_OK) s = timed(c, 1, [&] { return asp::launch_fit(q, c->stream); });
+    if (s == ASP_OK && !q.fuse_update)
         s = timed(c, 2, [&] { return asp::launch_update(c->P, c->update_grid, c->stream); });
     return s;
 }
