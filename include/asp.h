@@ -221,13 +221,17 @@ asp_status asp_fit_active_set(asp_ctx *ctx, int64_t idx, const asp_gauss *init,
  */
 asp_status asp_update_residual(asp_ctx *ctx, int64_t *pixels_touched);
 
-/* One full iteration (find_peak, fit, update) without host round trips. */
+/* One full iteration (find_peak, fit, update) without host round trips; the
+ * update runs as in asp_run. */
 asp_status asp_step(asp_ctx *ctx);
 
 /*
  * Up to n_iter iterations on the device.  Iterations are queued in chunks
  * with no host synchronisation inside a chunk; every kernel checks the
  * device stop flag, so the run stops exactly where the stop test fires.
+ * With update_launch 0 (the default) the residual update is done by the fit
+ * kernel's work-groups after the commit, in the same launch; with 1 it is a
+ * launch of its own.  The residual is the same bit for bit either way.
  * Returns ASP_OK (n_iter done), ASP_STOP_THRESHOLD or ASP_STOP_MAXITER.
  * rep may be NULL.
  */
