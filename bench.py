@@ -12,6 +12,9 @@ Besides the throughput the line carries:
                 context's stream over the timed region; its algorithmic work
                 is the FP32 Gram accumulation, (n+1)(n+2) flops per pixel
                 evaluation, against the FP32 vector peak
+  update_large  the residual update in its own launch on a field of the same
+                size holding one extended Gaussian: windows of millions of
+                pixels, the update's HBM rate when the work is large
   hbm           achieved HBM rates of the peak search (4 H W bytes per
                 launch) and, with --update-launch 1, of the residual update
                 (8 bytes per pixel read-modify-written); by default the
@@ -253,6 +256,43 @@ def peak_tiles_leg(args, f, rep, secs, ctx_full, torch, asp):
             out["achieved_gbs"] = bytes_it / (ms / n * 1e-3) / 1e9
     log(f"peak tiles {json.dumps(out)}")
     ctx.close()
+    return out
+
+
+def update_large_leg(args, f, torch, asp):
+    """The residual update on large windows: a field of the same size holding one
+    extended Gaussian (sigma 200 px, convolved), so that every iteration
+    rewrites a window of millions of pixels; the update in its own launch, timed
+    with HIP events, at 8 bytes per pixel read-modify-written."""
+    import numpy as np
+    H, W = f.shape
+    sig = 200.0
+    y = np.arange(H, dtype=np.float64)[:, None] - H / 2.0
+    x = np.arange(W, dtype=np.float64)[None, :] - W / 2.0
+    dirty = np.exp(-(x * x + y * y) / (2.0 * sig * sig)).astype(np.float32)
+    d_dirty = torch.from_numpy(dirty).cuda()
+    d_psf = torch.from_numpy(f.psf).cuda()
+    del dirty
+    n_iter = 20
+    ctx = asp.Context(d_dirty, d_psf, 0.1, 0.0, max_iter=n_iter + 2, max_active=1,
+                      update_launch=1)
+    del d_dirty, d_psf
+    ctx.run(2)
+    ctx.kernel_timing(True)
+    torch.cuda.synchronize()
+    rc, r = ctx.run(n_iter)
+    torch.cuda.synchronize()
+    ms, n = ctx.kernel_times()["update"]
+    ctx.close()
+    if not n or ms <= 0.0:
+        return None
+    b = 8.0 * r["pixels_updated"] / n
+    gbs = b / (ms / n * 1e-3) / 1e9
+    out = {"field": f"{H}x{W}, one Gaussian of sigma {sig:.0f} px, gain 0.1, active set of 1",
+           "launches": n, "pixels_per_launch": r["pixels_updated"] / n,
+           "bytes_per_launch": b, "avg_launch_us": ms / n * 1e3, "achieved_gbs": gbs,
+           "frac": gbs / PEAK_HBM_GBS}
+    log(f"update on large windows {json.dumps(out)}")
     return out
 
 
@@ -518,6 +558,8 @@ def main():
                     help="skip the smoothing-method (init mode 2) leg")
     ap.add_argument("--no-peak-tiles", action="store_true",
                     help="skip the incremental peak search leg")
+    ap.add_argument("--no-update-large", action="store_true",
+                    help="skip the update on large windows")
     ap.add_argument("--no-refresh", action="store_true",
                     help="skip the exact-PSF refresh leg")
     ap.add_argument("--no-2004", action="store_true",
@@ -645,6 +687,10 @@ def main():
     if not args.no_refresh:
         refresh = refresh_leg(args, f, rep, secs, ctx, torch, asp)
 
+    update_large = None
+    if not args.no_update_large and not args.no_kernel_events:
+        update_large = update_large_leg(args, f, torch, asp)
+
     asp2004 = None
     if not args.no_2004:
         asp2004 = asp2004_leg(args, f, rep, secs, torch, asp)
@@ -678,6 +724,7 @@ def main():
         "smoothing": smoothing,
         "peak_tiles": peak_tiles,
         "refresh": refresh,
+        "update_large": update_large,
         "asp2004_vs_2016": asp2004,
         "cpu_baseline": cpu,
     }

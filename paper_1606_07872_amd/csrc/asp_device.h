@@ -68,10 +68,10 @@ struct DevState {
     int32_t n_rects, pad0;
     Rect rects[kMaxRects];
     int32_t bb[4];                 // bounding box of the rects
-    unsigned long long update_px;
     // counters summed over iterations
     unsigned long long sum_trials, not_converged, fallbacks;
-    unsigned long long sum_update_px;   // pixels read-modify-written by the update
+    unsigned long long px_total;        // pixels read-modify-written by the updates so far
+                                        // (written by k_px_read from px_slots)
     unsigned long long sum_eval_px;     // pixel evaluations of the LM trials
     unsigned long long sum_gram_flops;  // (n+1)(n+2) per pixel evaluation
     // Gaussian main lobe of the PSF
@@ -99,6 +99,9 @@ struct DevState {
     double *sq_slots;
     int32_t sq_nslots, sq_pad;
     double sq_base;
+    // pixels rewritten by the updates, one running count per update
+    // work-group index (no two work-groups add to one counter)
+    unsigned long long *px_slots;
 };
 constexpr int kSqSlots = 4096;
 
@@ -337,6 +340,8 @@ hipError_t launch_propose(const Params &p, const NetParams &net, int use_net, hi
 // cleared, and read (base plus the slots in a fixed order) into *out.
 hipError_t launch_sq_rebase(DevState *st, const double *total, hipStream_t s);
 hipError_t launch_sq_read(DevState *st, double *out, hipStream_t s);
+// st->px_total = the sum of st->px_slots.
+hipError_t launch_px_read(DevState *st, hipStream_t s);
 hipError_t launch_sumsq(const float *img, int64_t n, double *part, int nblk, double *out,
                         hipStream_t s);
 hipError_t fit_kernel_setup();

@@ -223,12 +223,13 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
     if (t == 0) {
         unsigned long long c = cnt_s[0] + cnt_s[1] + cnt_s[2] + cnt_s[3];
         if (c) {
-            atomicAdd(&st->update_px, c);
-            atomicAdd(&st->sum_update_px, c);
-            // the work-group's own slot of the tracked sum of R^2: the same
-            // work-group index in every launch, so no two writers and a fixed order
-            if (st->sq_slots)
-                st->sq_slots[rank % st->sq_nslots] += ((dsq_s[0] + dsq_s[1]) + dsq_s[2]) + dsq_s[3];
+            // the work-group's own slots of the pixel count and of the tracked
+            // sum of R^2: the same work-group index in every launch, so no two
+            // writers (no atomics on one counter from every work-group) and a
+            // fixed order
+            const int slot = rank % st->sq_nslots;
+            st->px_slots[slot] += c;
+            st->sq_slots[slot] += ((dsq_s[0] + dsq_s[1]) + dsq_s[2]) + dsq_s[3];
         }
     }
 }

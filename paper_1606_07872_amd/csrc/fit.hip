@@ -1061,7 +1061,6 @@ __device__ __forceinline__ void commit(const Params &p, WGShared &S)
         p.c_updated[L] = k;
         st->n_rects = nr;
         st->bb[0] = bb[0]; st->bb[1] = bb[1]; st->bb[2] = bb[2]; st->bb[3] = bb[3];
-        st->update_px = 0ull;
         st->L = L + 1;
         st->k = k + 1;
         st->fit_ready = 1;

@@ -306,6 +306,27 @@ __global__ __launch_bounds__(256) void k_sq_read(DevState *st, double *out)
     }
 }
 
+// the pixel counts: integer sums, exact in any order
+__global__ __launch_bounds__(256) void k_px_read(DevState *st)
+{
+    __shared__ unsigned long long red[256];
+    unsigned long long v = 0;
+    for (int i = threadIdx.x; i < st->sq_nslots; i += blockDim.x) v += st->px_slots[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long sum = 0;
+        for (int i = 0; i < 256; ++i) sum += red[i];
+        st->px_total = sum;
+    }
+}
+
+hipError_t launch_px_read(DevState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_px_read, dim3(1), dim3(256), 0, s, st);
+    return hipGetLastError();
+}
+
 hipError_t launch_sq_rebase(DevState *st, const double *total, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sq_rebase, dim3(1), dim3(256), 0, s, st, total);

@@ -48,6 +48,7 @@ struct asp_ctx {
     asp::NetParams netp{};
     double *sumsq = nullptr;              // 1024 partials, the total, the tracked read
     double *sq_slots = nullptr;           // per update work-group deltas of the sum of R^2
+    unsigned long long *px_slots = nullptr;  // per update work-group pixel counts
     // the smoothing method's device buffers (allocated on first use)
     float *sm_vt = nullptr, *sm_taps = nullptr, *sm_w = nullptr, *sm_map = nullptr;
     unsigned long long *sm_keys = nullptr;
@@ -116,6 +117,7 @@ void release(asp_ctx *c)
     (void)hipFree(c->fg); (void)hipFree(c->partials); (void)hipFree(c->net);
     (void)hipFree(c->sumsq);
     (void)hipFree(c->sq_slots);
+    (void)hipFree(c->px_slots);
     (void)hipFree(c->sm_vt); (void)hipFree(c->sm_taps); (void)hipFree(c->sm_w);
     (void)hipFree(c->sm_map); (void)hipFree(c->sm_keys); (void)hipFree(c->sm_dirty);
     (void)hipFree(c->sm_list); (void)hipFree(c->sm_count);
@@ -348,6 +350,9 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     CREATE_HIP(dev_alloc(&c->st, 1));
     CREATE_HIP(dev_alloc(&c->sumsq, 1026));
     CREATE_HIP(dev_alloc(&c->sq_slots, asp::kSqSlots));
+    CREATE_HIP(dev_alloc(&c->px_slots, asp::kSqSlots));
+    CREATE_HIP(hipMemsetAsync(c->px_slots, 0, sizeof(unsigned long long) * asp::kSqSlots,
+                              c->stream));
     CREATE_HIP(dev_alloc(&c->work, np > 2 ? np : 2));
     const int fit_grid = asp::fit_grid_size(c->device);
     CREATE_HIP(dev_alloc(&c->fg, 1));
@@ -364,6 +369,7 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     c->st_host->forced_idx = -1;
     c->st_host->sq_slots = c->sq_slots;
     c->st_host->sq_nslots = asp::kSqSlots;
+    c->st_host->px_slots = c->px_slots;
     CREATE_HIP(hipMemcpyAsync(c->st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice,
                               c->stream));
     // NaN / Inf in either image is an error (no CPU scan: a device kernel).
@@ -566,6 +572,16 @@ asp_status rebase_sumsq(asp_ctx *c)
                                      c->stream));
     HIP_OR_FAIL(c, asp::launch_sq_rebase(c->st, c->sumsq + 1024, c->stream));
     return ASP_OK;
+}
+
+// The pixels rewritten by all updates so far (sum of the per work-group counts),
+// with the rest of the device state pulled to the host.
+asp_status pull_with_px(asp_ctx *c, unsigned long long *px)
+{
+    HIP_OR_FAIL(c, asp::launch_px_read(c->st, c->stream));
+    asp_status s = pull_all(c);
+    if (s == ASP_OK && px) *px = c->st_host->px_total;
+    return s;
 }
 
 // One refresh on the stream; then every tile of the incremental searches is
@@ -892,10 +908,13 @@ asp_status asp_update_residual(asp_ctx *c, int64_t *pixels_touched)
 {
     if (!c) return ASP_ERR_INVALID_ARG;
     if (c->phase != 2) return fail(c, ASP_ERR_STATE, "asp_update_residual needs a fit first");
-    HIP_OR_FAIL(c, asp::launch_update(c->P, c->update_grid, c->stream));
-    asp_status s = pull_all(c);
+    unsigned long long px0 = 0, px1 = 0;
+    asp_status s = pixels_touched ? pull_with_px(c, &px0) : ASP_OK;
     if (s != ASP_OK) return s;
-    if (pixels_touched) *pixels_touched = (int64_t)c->st_host->update_px;
+    HIP_OR_FAIL(c, asp::launch_update(c->P, c->update_grid, c->stream));
+    s = pull_with_px(c, &px1);
+    if (s != ASP_OK) return s;
+    if (pixels_touched) *pixels_touched = (int64_t)(px1 - px0);
     c->phase = 0;
     return ASP_OK;
 }
@@ -929,11 +948,12 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
 {
     if (!c || n_iter < 0) return ASP_ERR_INVALID_ARG;
     if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_run inside a step-API sequence");
-    asp_status s = pull_all(c);
+    unsigned long long up0 = 0, up1 = 0;
+    asp_status s = pull_with_px(c, &up0);
     if (s != ASP_OK) return s;
     const int64_t k0 = c->st_host->k;
     const unsigned long long t0 = c->st_host->sum_trials, nc0 = c->st_host->not_converged,
-                             fb0 = c->st_host->fallbacks, up0 = c->st_host->sum_update_px,
+                             fb0 = c->st_host->fallbacks,
                              ep0 = c->st_host->sum_eval_px, gf0 = c->st_host->sum_gram_flops,
                              sm0 = c->st_host->sum_smoothed, pk0 = c->st_host->pk_tiles_done;
     const int every = c->opt.refresh_every;
@@ -966,6 +986,8 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
         if (result == ASP_OK && done == before)
             return fail(c, ASP_ERR_STATE, "no iteration progressed and no stop was set");
     }
+    s = pull_with_px(c, &up1);
+    if (s != ASP_OK) return s;
     if (rep) {
         rep->iterations = c->st_host->k - k0;
         rep->total_iterations = c->st_host->k;
@@ -973,7 +995,7 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
         rep->lm_trials = (int64_t)(c->st_host->sum_trials - t0);
         rep->not_converged = (int64_t)(c->st_host->not_converged - nc0);
         rep->fallbacks = (int64_t)(c->st_host->fallbacks - fb0);
-        rep->pixels_updated = (int64_t)(c->st_host->sum_update_px - up0);
+        rep->pixels_updated = (int64_t)(up1 - up0);
         rep->pixels_evaluated = (int64_t)(c->st_host->sum_eval_px - ep0);
         rep->gram_flops = (int64_t)(c->st_host->sum_gram_flops - gf0);
         rep->smoothed = (int64_t)(c->st_host->sum_smoothed - sm0);
