@@ -69,19 +69,29 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+FIT_SOURCES = ("fit.hip", "cycle.h", "asp_device.h")   # what the fit kernel is built from
+
+
+def fit_source_digest() -> str:
+    """SHA-256 over the fit kernel's sources, in FIT_SOURCES order."""
+    h = hashlib.sha256()
+    for name in FIT_SOURCES:
+        with open(os.path.join(ROOT, "paper_1606_07872_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def fit_traffic(workload: str, fit_launches: int):
     """HBM bytes per fit launch from the committed PMC summary, if it was taken
-    on the current fit kernel source; else None."""
+    on the current fit kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"k_fit_{workload}_traffic.json")
-    src = os.path.join(ROOT, "paper_1606_07872_amd", "csrc", "fit.hip")
     try:
         with open(path) as fh:
             rec = json.load(fh)
-        with open(src, "rb") as fh:
-            digest = hashlib.sha256(fh.read()).hexdigest()
+        digest = fit_source_digest()
     except (OSError, ValueError):
         return None
-    if rec.get("fit_hip_sha256") != digest:
+    if rec.get("fit_sources_sha256") != digest:
         return None
     return rec.get("bytes_per_launch")
 

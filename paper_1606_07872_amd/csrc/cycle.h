@@ -118,13 +118,18 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
     // wave keeps several loads in flight
     constexpr int kUpdRows = 16, kPer = kUpdRows / 4;
     const int ntx = (bc1 - bc0 + 64) / 64, nty = (br1 - br0 + kUpdRows) / kUpdRows;
-    const int64_t ntiles = (int64_t)ntx * nty;
-    unsigned long long cnt = 0;
+    // a bounding box lies inside the image (fewer than 2^32 pixels), so tile
+    // indices fit in 32 bits
+    const int32_t ntiles = ntx * nty;
+    static_assert(kMaxRects <= 32, "one bit per rect");
+    uint32_t cnt32 = 0;
     double dsq = 0.0;                   // change of the sum of R^2 over this thread's pixels
     const int lr = t >> 6, lc = t & 63;
-    for (int64_t tile = rank; tile < ntiles; tile += size) {
-        const int32_t tr0 = br0 + (int32_t)(tile / ntx) * kUpdRows;
-        const int32_t tc0 = bc0 + (int32_t)(tile % ntx) * 64;
+    const int64_t rstride = 4 * (int64_t)p.W;   // rows lr, lr + 4, ... of a tile
+    for (int32_t tile = rank; tile < ntiles; tile += size) {
+        const int32_t ty = tile / ntx;
+        const int32_t tr0 = br0 + ty * kUpdRows;
+        const int32_t tc0 = bc0 + (tile - ty * ntx) * 64;
         bool any = false;
         for (int i = 0; i < nr; ++i)
             any |= (rb[i][0] <= tr0 + kUpdRows - 1 && tr0 <= rb[i][1] && rb[i][2] <= tc0 + 63 &&
@@ -132,6 +137,11 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
         if (!any) continue;
         const int32_t c = tc0 + lc;
         if (c > bc1) continue;
+        // the rects whose columns hold this thread's column (fixed in a tile)
+        uint32_t colmask = 0u;
+        for (int i = 0; i < nr; ++i)
+            colmask |= (c >= rb[i][2] && c <= rb[i][3]) ? (1u << i) : 0u;
+        const int64_t q = (int64_t)(tr0 + lr) * p.W + c;   // pixel k at q + k * rstride
         float acc[kPer], val[kPer];
         bool hit[kPer];
 #pragma unroll
@@ -141,17 +151,16 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
             hit[k] = false;
             if (r > br1) continue;
             for (int i = 0; i < nr; ++i)
-                hit[k] |= !(r < rb[i][0] || r > rb[i][1] || c < rb[i][2] || c > rb[i][3]);
+                hit[k] |= ((colmask >> i) & 1u) && r >= rb[i][0] && r <= rb[i][1];
         }
 #pragma unroll
-        for (int k = 0; k < kPer; ++k)
-            val[k] = hit[k] ? p.R[(int64_t)(tr0 + lr + 4 * k) * p.W + c] : 0.0f;
+        for (int k = 0; k < kPer; ++k) val[k] = hit[k] ? p.R[q + k * rstride] : 0.0f;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             if (!hit[k]) continue;
             const int32_t r = tr0 + lr + 4 * k;
             for (int i = 0; i < nr; ++i) {
-                if (r < rb[i][0] || r > rb[i][1] || c < rb[i][2] || c > rb[i][3]) continue;
+                if (!((colmask >> i) & 1u) || r < rb[i][0] || r > rb[i][1]) continue;
                 float dx = (float)(c - rcx[i]) - rfx[i];
                 float dy = (float)(r - rcy[i]) - rfy[i];
                 acc[k] += ramp[i] * __expf(-(dx * dx + dy * dy) * rinv[i]);
@@ -161,11 +170,12 @@ __device__ inline void update_tiles(const Params &p, int rank, int size)
         for (int k = 0; k < kPer; ++k) {
             if (!hit[k]) continue;
             const float nv = val[k] + acc[k];
-            p.R[(int64_t)(tr0 + lr + 4 * k) * p.W + c] = nv;
+            p.R[q + k * rstride] = nv;
             dsq += (double)nv * nv - (double)val[k] * val[k];
-            ++cnt;
+            ++cnt32;
         }
     }
+    unsigned long long cnt = cnt32;
     if (p.sm.n > 0 && rank == 0) {
         // tiles of the smoothed images that these windows make stale: per
         // scale j, rows within h_j of a window for the column pass, rows and
