@@ -62,3 +62,31 @@ def test_update_launch_option_is_checked():
         make(f, update_launch=2)
     with pytest.raises(asp.AspError):
         make(f, reserved=1)
+
+
+def test_fused_update_on_windows_of_millions_of_pixels():
+    """One extended Gaussian (sigma 150 px) on a 2048^2 field: every update
+    rewrites more than 1024^2 pixels, so each work-group of both paths (256
+    in the fit kernel, 4 per CU in its own launch) takes several tiles."""
+    n, sig = 2048, 150.0
+    y = np.arange(n, dtype=np.float64)[:, None] - n / 2.0
+    x = np.arange(n, dtype=np.float64)[None, :] - n / 2.0
+    dirty = np.exp(-(x * x + y * y) / (2.0 * sig * sig)).astype(np.float32)
+    psf = skygen.gaussian_psf(33, 3.0).astype(np.float32)
+    ctxs = [asp.Context(dirty, psf, 0.1, 0.0, max_iter=10, max_active=1, update_launch=u)
+            for u in (0, 1)]
+    reps = [c.run(5) for c in ctxs]
+    assert reps[0] == reps[1]
+    assert reps[0][1]["pixels_updated"] > 5 * 1024 * 1024
+    a, b = ctxs
+    assert np.array_equal(a.residual(), b.residual())
+    assert np.array_equal(a.components_raw(), b.components_raw())
+    # the step API's count of one more update equals the run's
+    rc, idx, _ = b.find_peak()
+    b.fit_active_set(idx)
+    px = b.update_residual()
+    rc, r = a.run(1)
+    assert r["pixels_updated"] == px > 1024 * 1024
+    assert np.array_equal(a.residual(), b.residual())
+    for c in ctxs:
+        c.close()
