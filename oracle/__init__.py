@@ -105,6 +105,10 @@ def lib():
                                      ctypes.c_void_p]
         L.orc_run.argtypes = [ctypes.POINTER(_State), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         L.orc_residual_from_scratch.argtypes = [ctypes.POINTER(_State), dp, dp]
+        L.orc_fit_eval.argtypes = [ctypes.POINTER(_State), ctypes.c_int, dp, dp, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64)]
+        L.orc_fit_eval.restype = ctypes.c_double
         L.orc_fit_gaussians.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_double,
@@ -325,6 +329,23 @@ class Oracle:
         done = ctypes.c_int64()
         rc = lib().orc_run(ctypes.byref(self.st), n_iter, ctypes.byref(done))
         return rc, done.value
+
+    def fit_eval(self, theta, stored=None) -> dict:
+        """One evaluation of the fit objective on the current residual: theta
+        (m, 4) with the new component first, stored (m, 4) the old members'
+        stored parameters (row 0 unused).  Returns F, H = J^T J, g = J^T (D - M),
+        chi2 and the pixel count of U."""
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, 4))
+        m = th.shape[0]
+        sd = np.zeros_like(th) if stored is None else np.ascontiguousarray(
+            np.asarray(stored, dtype=np.float64).reshape(m, 4))
+        n = 4 * m
+        H = np.zeros((n, n))
+        g = np.zeros(n)
+        chi2, npx = ctypes.c_double(), ctypes.c_int64()
+        F = lib().orc_fit_eval(ctypes.byref(self.st), m, th.ravel(), sd.ravel(), H.ctypes.data,
+                               g.ctypes.data, ctypes.byref(chi2), ctypes.byref(npx))
+        return {"F": F, "H": H, "g": g, "chi2": chi2.value, "npx": int(npx.value)}
 
     def residual_from_scratch(self) -> np.ndarray:
         out = np.zeros_like(self.dirty)

@@ -265,6 +265,22 @@ static double fit_eval(const fit_problem *fp, const double *theta, double *Hs, d
     return F;
 }
 
+double orc_fit_eval(const orc_state *st, int m, const double *theta, const double *stored,
+                    double *H, double *g, double *chi2, int64_t *npx)
+{
+    if (m < 1 || m > ORC_MAX_ACTIVE) return NAN;
+    fit_problem fp;
+    memset(&fp, 0, sizeof fp);
+    fp.st = st;
+    fp.m = m;
+    fp.data = st->R;
+    for (int j = 1; j < m; ++j) {
+        memcpy(fp.old + 4 * j, stored + 4 * j, 4 * sizeof(double));
+        comp_window(st, stored[4 * j + 1], stored[4 * j + 2], stored[4 * j + 3], fp.wold[j]);
+    }
+    return fit_eval(&fp, theta, H, g, chi2, npx);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Levenberg-Marquardt (Marquardt 1963), as used in Sect. 3 for Eq. (4).     */
 /* Readings: the damped system (H + mu D) delta = g with                     */
@@ -778,6 +794,10 @@ int orc_fit_gaussians(const double *data, int64_t H, int64_t W, int m, double *t
     fp.st = &st;
     fp.m = m;
     fp.data = data;
+    /* no old members to add back: every stored window is empty */
+    for (int j = 0; j < m; ++j) {
+        fp.wold[j][0] = 0; fp.wold[j][1] = -1; fp.wold[j][2] = 0; fp.wold[j][3] = -1;
+    }
     set_bounds(&fp, theta);
     lm_result r = lm_fit(&fp, theta, lm_max_iter, mu0, tol, NULL);
     if (converged) *converged = r.converged;

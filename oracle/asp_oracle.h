@@ -124,6 +124,16 @@ int orc_run(orc_state *st, int64_t n_iter, int64_t *done);
 /* out = dirty - sum_j G_j on W_j  (the residual from its definition). */
 void orc_residual_from_scratch(const orc_state *st, const double *dirty, double *out);
 
+/* One evaluation of the fit objective (Eq. 4 on the union U of the members'
+ * windows, the data being R with the old members' stored Gaussians added back
+ * on their stored windows): returns F = sum_U M (M - 2 D); H (n x n, n = 4 m,
+ * nullable) = J^T J, g (n, nullable) = J^T (D - M), chi2 (nullable) =
+ * sum_U (D - M)^2, npx (nullable) = |U|.  theta holds the m members' (a, x,
+ * y, s), the new component first; stored[4 j .. 4 j + 3] the stored
+ * parameters of old member j >= 1 (stored[0..3] unused).  Data: st->R. */
+double orc_fit_eval(const orc_state *st, int m, const double *theta, const double *stored,
+                    double *H, double *g, double *chi2, int64_t *npx);
+
 /* One LM fit of m Gaussians (theta, updated in place) to a data image with no
  * add-back of old components, by the same objective and LM as orc_step.
  * Returns the trials used. */
