@@ -99,6 +99,10 @@ typedef struct {
                                     the simple values and LM started from it     */
     double init[4];              /* the proposal (a, x, y, s) before clamping, or
                                     the smoothing method's start                 */
+    int32_t added;               /* 1: the new component joined the list; 0: its
+                                    fitted amplitude is zero (the old members
+                                    explain the peak) and it was not added       */
+    int32_t pad2;
 } asp_fit_report;
 
 typedef struct {
@@ -161,6 +165,8 @@ typedef struct {
     int64_t smoothed;            /* fits started from the smoothing method       */
     int64_t peak_tiles_scanned;  /* 64 x 64 tiles rescanned by the incremental
                                     peak search (peak_tiles = 1)                 */
+    int64_t not_added;           /* fits whose new component had amplitude zero
+                                    and was not added                            */
 } asp_run_report;
 
 /* Fill *opt with the defaults above. */
@@ -213,13 +219,23 @@ asp_status asp_fit_active_set(asp_ctx *ctx, int64_t idx, const asp_gauss *init,
                               asp_fit_report *rep);
 
 /*
- * Step 4 (Sect. 3 loop gain; Sect. 2 step 3 with the Gaussian beam): commit
- * the fit (new component with the loop gain, old members replaced by their
- * refits) and update the residual on the windows involved.  Must follow
+ * Step 4 (Sect. 3 loop gain; Sect. 2 step 3 with the Gaussian beam): the fit's
+ * commit, made on the device at the end of asp_fit_active_set, changes the
+ * model by the loop gain times the fitted change -- the new component joins
+ * with gain times its fitted amplitude (not at all when that amplitude is
+ * zero), each old member moves the fraction gain of the way to its refit --
+ * and this call updates the residual on the windows involved.  Must follow
  * asp_fit_active_set.  pixels_touched (nullable) receives the read-modify-
  * written pixel count.
  */
 asp_status asp_update_residual(asp_ctx *ctx, int64_t *pixels_touched);
+
+/*
+ * The report of the last fit made by any path (the step API, asp_step,
+ * asp_run or a batched launch), read from the device state.  rep must not be
+ * NULL.
+ */
+asp_status asp_last_fit(asp_ctx *ctx, asp_fit_report *rep);
 
 /* One full iteration (find_peak, fit, update) without host round trips; the
  * update runs as in asp_run. */

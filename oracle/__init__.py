@@ -72,7 +72,8 @@ class _Report(ctypes.Structure):
                 ("chi2_init", ctypes.c_double), ("chi2_final", ctypes.c_double),
                 ("theta", ctypes.c_double * (4 * MAX_ACTIVE)),
                 ("theta0", ctypes.c_double * (4 * MAX_ACTIVE)),
-                ("omega_px", ctypes.c_int64), ("update_px", ctypes.c_int64)]
+                ("omega_px", ctypes.c_int64), ("update_px", ctypes.c_int64),
+                ("added", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -303,7 +304,8 @@ class Oracle:
                "chi2_init": rep.chi2_init, "chi2_final": rep.chi2_final,
                "theta": np.array(rep.theta[: 4 * m]).reshape(-1, 4),
                "theta0": np.array(rep.theta0[: 4 * m]).reshape(-1, 4),
-               "omega_px": int(rep.omega_px), "update_px": int(rep.update_px)}
+               "omega_px": int(rep.omega_px), "update_px": int(rep.update_px),
+               "added": bool(rep.added)}
         if want_hess and m:
             n = 4 * m
             out["hess"] = hess[: n * n].reshape(n, n).copy()

@@ -713,26 +713,38 @@ static int step_impl(orc_state *st, const double *init, const double *start4, or
     rep->chi2_init = lmr.chi2_0;
     rep->chi2_final = lmr.chi2;
 
-    /* Commit and residual update (Sect. 2 step 3 with B = the Gaussian beam):
-     * each old member is added back on its old window and subtracted as
-     * refitted on its new window; the new component joins with the loop gain
-     * applied to its amplitude (Sect. 3). */
+    /* Commit and residual update (Sect. 2 step 3 with B = the Gaussian beam).
+     * Reading of the loop gain (Sect. 3): every change the fit makes to the
+     * model image is scaled by the gain.  The new component joins with gain
+     * times its fitted amplitude, at its fitted centre and width; each old
+     * member moves the fraction gain of the way from its stored parameters to
+     * its refit, t_j <- t_j + gain (t*_j - t_j), and is added back on its old
+     * window and subtracted on its new one.  A new component whose fitted
+     * amplitude is zero (held on its sign bound: the old members explain the
+     * peak) models no emission and is not added to the list. */
     int64_t touched = 0;
+    const double g = st->gain;
     for (int j = 1; j < m; ++j) {
         orc_comp *cj = &st->comps[rep->members[j]];
         add_window(st, cj->a, cj->x, cj->y, cj->s, +1.0, &touched);
         const double *t = theta + 4 * j;
-        cj->a = t[0]; cj->x = t[1]; cj->y = t[2]; cj->s = t[3];
+        cj->a = cj->a + g * (t[0] - cj->a);
+        cj->x = cj->x + g * (t[1] - cj->x);
+        cj->y = cj->y + g * (t[2] - cj->y);
+        cj->s = cj->s + g * (t[3] - cj->s);
         cj->iter_updated = st->k;
         add_window(st, cj->a, cj->x, cj->y, cj->s, -1.0, &touched);
     }
-    orc_comp *cn = &st->comps[st->L];
-    cn->a = st->gain * theta[0];
-    cn->x = theta[1]; cn->y = theta[2]; cn->s = theta[3];
-    cn->iter_added = st->k;
-    cn->iter_updated = st->k;
-    add_window(st, cn->a, cn->x, cn->y, cn->s, -1.0, &touched);
-    st->L += 1;
+    rep->added = theta[0] != 0.0;
+    if (rep->added) {
+        orc_comp *cn = &st->comps[st->L];
+        cn->a = g * theta[0];
+        cn->x = theta[1]; cn->y = theta[2]; cn->s = theta[3];
+        cn->iter_added = st->k;
+        cn->iter_updated = st->k;
+        add_window(st, cn->a, cn->x, cn->y, cn->s, -1.0, &touched);
+        st->L += 1;
+    }
     st->k += 1;
     rep->update_px = touched;
     rep->status = lmr.converged ? ORC_OK : ORC_LM_NOT_CONVERGED;

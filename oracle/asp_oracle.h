@@ -15,7 +15,9 @@
  *     PSF-convolved component written as an analytic Gaussian (no FFT).
  *   - Sect. 3, Eqs. (5)-(6): the component is recovered from the fitted
  *     Gaussian by analytic deconvolution of the Gaussian main lobe.
- *   - Sect. 3: a loop gain scales the new component before it joins the model.
+ *   - Sect. 3: a loop gain scales the new component before it joins the model;
+ *     read here as scaling every change of the model image, so a refitted old
+ *     member of the active set moves the fraction gain toward its refit.
  *   - Sect. 3: the simple initial values (the residual peak and the main-lobe
  *     width of the PSF).
  * Readings where the paper is silent (active set, windows, LM constants) are
@@ -66,10 +68,13 @@ typedef struct {
     int32_t lm_iters, converged, used_fallback;
     int32_t start_from_proposal; /* LM started from the proposal (it scored lower) */
     double chi2_init, chi2_final;
-    double theta[4 * ORC_MAX_ACTIVE]; /* fitted (a,x,y,s) per member, pre-gain */
+    double theta[4 * ORC_MAX_ACTIVE]; /* fitted (a,x,y,s) per member, before the
+                                         loop gain moves the list toward it     */
     double theta0[4 * ORC_MAX_ACTIVE];/* starting point of the fit            */
     int64_t omega_px;           /* pixels of U(theta) at the fitted theta     */
     int64_t update_px;          /* pixels read-modify-written by the update   */
+    int32_t added;              /* 1: the new component joined the list (its   */
+    int32_t pad;                /*    fitted amplitude is not zero)            */
 } orc_report;
 
 enum { ORC_OK = 0, ORC_STOP_THRESHOLD = 1, ORC_STOP_MAXITER = 2, ORC_LM_NOT_CONVERGED = 3,

@@ -23,6 +23,7 @@ MAX_SCALES = 8
 # Every symbol include/asp.h declares.
 EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destroy",
            "asp_last_error", "asp_find_peak", "asp_fit_active_set", "asp_update_residual",
+           "asp_last_fit",
            "asp_step", "asp_run", "asp_components", "asp_components_raw", "asp_residual",
            "asp_residual_device", "asp_psf_gauss", "asp_counts", "asp_fit_profile",
            "asp_kernel_timing", "asp_kernel_times", "asp_set_mlp", "asp_set_init_mode",
@@ -82,7 +83,8 @@ class FitReport(ctypes.Structure):
                 ("theta0", ctypes.c_double * (4 * MAX_ACTIVE)),
                 ("theta", ctypes.c_double * (4 * MAX_ACTIVE)),
                 ("fit_px", ctypes.c_int64), ("init_source", ctypes.c_int32),
-                ("start_from_proposal", ctypes.c_int32), ("init", ctypes.c_double * 4)]
+                ("start_from_proposal", ctypes.c_int32), ("init", ctypes.c_double * 4),
+                ("added", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 class Fit2004Report(ctypes.Structure):
@@ -106,7 +108,7 @@ class RunReport(ctypes.Structure):
                 ("not_converged", ctypes.c_int64), ("fallbacks", ctypes.c_int64),
                 ("pixels_updated", ctypes.c_int64), ("pixels_evaluated", ctypes.c_int64),
                 ("gram_flops", ctypes.c_int64), ("smoothed", ctypes.c_int64),
-                ("peak_tiles_scanned", ctypes.c_int64)]
+                ("peak_tiles_scanned", ctypes.c_int64), ("not_added", ctypes.c_int64)]
 
 
 COMPONENT_DTYPE = np.dtype([("flux", "<f8"), ("amp", "<f8"), ("x", "<f8"), ("y", "<f8"),
@@ -136,6 +138,7 @@ def lib():
         L.asp_find_peak.argtypes = [vp, P(i64), P(f32)]
         L.asp_fit_active_set.argtypes = [vp, i64, P(Gauss), P(FitReport)]
         L.asp_update_residual.argtypes = [vp, P(i64)]
+        L.asp_last_fit.argtypes = [vp, P(FitReport)]
         L.asp_step.argtypes = [vp]
         L.asp_run.argtypes = [vp, i64, P(RunReport)]
         L.asp_components.argtypes = [vp, vp, i64, P(i64)]
@@ -274,6 +277,12 @@ class Context:
         rc = self._check(lib().asp_fit_active_set(self._ctx, idx, ctypes.byref(g) if g else None,
                                                    ctypes.byref(rep)))
         return rc, report_dict(rep)
+
+    def last_fit(self) -> dict:
+        """The report of the last fit (step API, run or batch)."""
+        rep = FitReport()
+        self._check(lib().asp_last_fit(self._ctx, ctypes.byref(rep)))
+        return report_dict(rep)
 
     def update_residual(self) -> int:
         n = ctypes.c_int64()
@@ -621,7 +630,7 @@ def report_dict(rep: FitReport) -> dict:
             "theta0": np.array(rep.theta0[: 4 * m]).reshape(-1, 4),
             "theta": np.array(rep.theta[: 4 * m]).reshape(-1, 4), "fit_px": rep.fit_px,
             "init_source": rep.init_source, "init": np.array(rep.init[:4]),
-            "start_from_proposal": bool(rep.start_from_proposal)}
+            "start_from_proposal": bool(rep.start_from_proposal), "added": bool(rep.added)}
 
 
 # The C names, for callers that prefer them.

@@ -64,12 +64,15 @@ struct DevState {
     double chi2_init, chi2_final;
     double theta0[kMaxN], theta[kMaxN];
     int64_t fit_px;
+    int32_t added;                 // the new component joined the list
+    int32_t pad_a;
     // update plan
     int32_t n_rects, pad0;
     Rect rects[kMaxRects];
     int32_t bb[4];                 // bounding box of the rects
     // counters summed over iterations
     unsigned long long sum_trials, not_converged, fallbacks;
+    unsigned long long not_added;       // fits whose new component had amplitude zero
     unsigned long long px_total;        // pixels read-modify-written by the updates so far
                                         // (written by k_px_read from px_slots)
     unsigned long long sum_eval_px;     // pixel evaluations of the LM trials
@@ -119,6 +122,7 @@ struct FitGlobal {
     double th_e[kMaxN];                 // parameters under evaluation
     double th_old[kMaxN];               // stored parameters of the old members
     unsigned int gen;                   // publication counter
+    unsigned int beat;                  // the batched leader's iteration heartbeat
     unsigned int top;                   // second-level arrivals (one per group)
     unsigned int arrive_g[kMaxGroups];  // first-level arrivals (one per work-group)
 };
@@ -345,6 +349,10 @@ hipError_t launch_px_read(DevState *st, hipStream_t s);
 hipError_t launch_sumsq(const float *img, int64_t n, double *part, int nblk, double *out,
                         hipStream_t s);
 hipError_t fit_kernel_setup();
+// Work-groups of the cooperative fit launch: every one resident at once (the
+// occupancy at the kernel's LDS times the CUs) -- 0 when the kernel needs a
+// private segment (scratch), with which the waves of one launch are not
+// guaranteed to be resident together.
 int fit_grid_size(int device);
 
 // The batched kernel: many fields, one persistent launch (fit.hip).
@@ -360,6 +368,9 @@ struct BatchArgs {
     unsigned long long spin_ticks; // time bound of every wait between work-groups
     int32_t n_fields, team_size, solo_tiles, min_tiles;
 };
+// Work-groups of the persistent batched launch, whole XCD rows that are all
+// resident at once; 0 when that cannot be guaranteed (a private segment, or
+// no occupancy).
 int batch_grid_size(int device);
 hipError_t launch_batch(const BatchArgs &b, int grid, hipStream_t s);
 

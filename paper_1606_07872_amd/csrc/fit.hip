@@ -121,16 +121,28 @@ __device__ inline int32_t ld_shared(const int32_t *q)
     return __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Every wait is bounded in time: `limit` device wall-clock ticks.
+// Every wait is bounded in time: `limit` device wall-clock ticks.  With
+// `beat`, the bound restarts whenever the heartbeat moves: a leader that
+// works alone for a long time (small fields of a batch) keeps its followers
+// waiting without letting them time out.
 __device__ __forceinline__ bool wait_publish(FitGlobal *G, WGShared &S, unsigned long long limit,
-                                             bool acquire = true)
+                                             bool acquire = true, bool beat = false)
 {
     if (threadIdx.x == 0) {
         unsigned int now = S.gen;
-        const unsigned long long t0 = now_ticks();
+        unsigned int last_beat = beat ? __hip_atomic_load(&G->beat, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        unsigned long long t0 = now_ticks();
         for (;;) {
             now = __hip_atomic_load(&G->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (now != S.gen || now_ticks() - t0 > limit) break;
+            if (now != S.gen) break;
+            const unsigned long long tn = now_ticks();
+            if (beat) {
+                const unsigned int b = __hip_atomic_load(&G->beat, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                if (b != last_beat) { last_beat = b; t0 = tn; }
+            }
+            if (tn - t0 > limit) break;
             __builtin_amdgcn_s_sleep(1);
         }
         S.abort = (now == S.gen) ? 1 : 0;
@@ -984,8 +996,13 @@ __device__ __forceinline__ void lm_step(const Params &p, WGShared &S, double *H2
     __syncthreads();
 }
 
-// Commit (Sect. 3: the loop gain on the new component; refits replace the
-// old members) and the residual-update plan.  Work-group 0.
+// Commit and the residual-update plan, work-group 0.  The loop gain (Sect. 3)
+// scales every change the fit makes to the model image: the new component
+// joins with gain times its fitted amplitude at its fitted centre and width,
+// and each old member moves the fraction gain of the way from its stored
+// parameters to its refit.  A new component whose fitted amplitude is zero
+// (held on its sign bound: the old members explain the peak) models no
+// emission and is not added to the list.
 __device__ __forceinline__ void commit(const Params &p, WGShared &S)
 {
     DevState *st = p.st;
@@ -1049,19 +1066,29 @@ __device__ __forceinline__ void commit(const Params &p, WGShared &S)
         for (int j = 1; j < m; ++j) {
             const int64_t cj = S.members[j];
             const double *to = S.th_old + 4 * j, *tn = S.th_c + 4 * j;
+            double tc[4];
+            // t + gain (t* - t), each operation rounded on its own
+            for (int q = 0; q < 4; ++q)
+                tc[q] = __dadd_rn(to[q], __dmul_rn(p.gain, __dsub_rn(tn[q], to[q])));
             add_rect(to[0], to[1], to[2], to[3], +1.0f);
-            add_rect(tn[0], tn[1], tn[2], tn[3], -1.0f);
-            p.ca[cj] = tn[0]; p.cx[cj] = tn[1]; p.cy[cj] = tn[2]; p.cs[cj] = tn[3];
+            add_rect(tc[0], tc[1], tc[2], tc[3], -1.0f);
+            p.ca[cj] = tc[0]; p.cx[cj] = tc[1]; p.cy[cj] = tc[2]; p.cs[cj] = tc[3];
             p.c_updated[cj] = k;
         }
-        const double anew = p.gain * S.th_c[0];
-        add_rect(anew, S.th_c[1], S.th_c[2], S.th_c[3], -1.0f);
-        p.ca[L] = anew; p.cx[L] = S.th_c[1]; p.cy[L] = S.th_c[2]; p.cs[L] = S.th_c[3];
-        p.c_added[L] = k;
-        p.c_updated[L] = k;
+        const bool added = S.th_c[0] != 0.0;
+        if (added) {
+            const double anew = __dmul_rn(p.gain, S.th_c[0]);
+            add_rect(anew, S.th_c[1], S.th_c[2], S.th_c[3], -1.0f);
+            p.ca[L] = anew; p.cx[L] = S.th_c[1]; p.cy[L] = S.th_c[2]; p.cs[L] = S.th_c[3];
+            p.c_added[L] = k;
+            p.c_updated[L] = k;
+        }
+        st->added = added ? 1 : 0;
+        st->not_added += added ? 0ull : 1ull;
         st->n_rects = nr;
+        if (nr == 0) { bb[0] = 0; bb[1] = -1; bb[2] = 0; bb[3] = -1; }
         st->bb[0] = bb[0]; st->bb[1] = bb[1]; st->bb[2] = bb[2]; st->bb[3] = bb[3];
-        st->L = L + 1;
+        st->L = added ? L + 1 : L;
         st->k = k + 1;
         st->fit_ready = 1;
     }
@@ -1406,7 +1433,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
 
     if (rank != 0) {
         for (;;) {
-            if (!wait_publish(G, S, b.spin_ticks)) return;      // the leader marks its field
+            if (!wait_publish(G, S, b.spin_ticks, true, true)) return;  // the leader marks its field
             if (t == 0) {
                 S.cmd = G->cmd;
                 S.fld = G->field;
@@ -1457,7 +1484,11 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
             S.k_target = P.st->k + b.n_iter;
         }
         for (;;) {
-            if (t == 0) S.go = (P.st->stop == 0 && P.st->k < S.k_target) ? 1 : 0;
+            if (t == 0) {
+                S.go = (P.st->stop == 0 && P.st->k < S.k_target) ? 1 : 0;
+                // one heartbeat per iteration: the followers' waits restart
+                __hip_atomic_fetch_add(&G->beat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             __syncthreads();
             if (!S.go) break;
             // the peak of |R| (Sect. 2 step 1)
@@ -1514,15 +1545,27 @@ hipError_t fit_kernel_setup()
                                (int)kFitLds);
 }
 
+// A kernel whose work-groups wait for each other must have all of them
+// resident at once.  A private segment (scratch) breaks that guarantee: the
+// waves of a dispatch can be held back until scratch is free.
+static bool no_private_segment(const void *kernel)
+{
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, kernel) != hipSuccess) return false;
+    return a.localSizeBytes == 0;
+}
+
 int batch_grid_size(int device)
 {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
+    if (!no_private_segment((const void *)k_batch)) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch, kT,
                                                      kFitLds) != hipSuccess || per_cu < 1)
         return 0;
-    return (cus * per_cu / 8) * 8;      // whole XCD rows
+    const int grid = (cus * per_cu / 8) * 8;      // whole XCD rows
+    return grid <= cus * per_cu ? grid : 0;
 }
 
 hipError_t launch_batch(const BatchArgs &b, int grid, hipStream_t s)
@@ -1536,13 +1579,14 @@ int fit_grid_size(int device)
 {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
-        return 1;
+        return 0;
+    if (!no_private_segment((const void *)k_fit)) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fit, kT, kFitLds) !=
             hipSuccess || per_cu < 1)
-        return 1;
+        return 0;
     int g = cus * per_cu;
     if (g > kGroup * kMaxGroups) g = kGroup * kMaxGroups;
-    return g < 1 ? 1 : g;
+    return g;
 }
 
 hipError_t launch_fit(const Params &p, hipStream_t s)

@@ -355,6 +355,11 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
                               c->stream));
     CREATE_HIP(dev_alloc(&c->work, np > 2 ? np : 2));
     const int fit_grid = asp::fit_grid_size(c->device);
+    if (fit_grid < 1) {
+        c->err = "the fit kernel's work-groups cannot all be resident at once (private segment "
+                 "or no occupancy): its cooperative launch is refused";
+        return bail(ASP_ERR_DEVICE);
+    }
     CREATE_HIP(dev_alloc(&c->fg, 1));
     CREATE_HIP(dev_alloc(&c->partials, (size_t)(fit_grid + asp::kMaxGroups) * asp::kPartStride));
     CREATE_HIP(hipMemsetAsync(c->fg, 0, sizeof(asp::FitGlobal), c->stream));
@@ -785,6 +790,30 @@ int64_t state_bytes(int64_t H, int64_t W, int64_t L)
 }
 }  // namespace
 
+// The report of the last fit from the host mirror of the device state.
+void fill_report(const DevState *h, asp_fit_report *rep)
+{
+    memset(rep, 0, sizeof *rep);
+    rep->n_active = h->n_active;
+    for (int i = 0; i < h->n_active; ++i) rep->members[i] = h->members[i];
+    rep->lm_iters = h->lm_iters;
+    rep->converged = h->converged;
+    rep->used_fallback = h->used_fallback;
+    rep->idx = h->idx;
+    rep->peak = h->peak;
+    rep->chi2_init = h->chi2_init;
+    rep->chi2_final = h->chi2_final;
+    for (int i = 0; i < 4 * h->n_active; ++i) {
+        rep->theta0[i] = h->theta0[i];
+        rep->theta[i] = h->theta[i];
+    }
+    rep->fit_px = h->fit_px;
+    rep->init_source = h->init_source;
+    rep->start_from_proposal = h->start_prop;
+    for (int i = 0; i < 4; ++i) rep->init[i] = h->init[i];
+    rep->added = h->added;
+}
+
 extern "C" {
 
 asp_status asp_default_options(asp_options *opt)
@@ -880,29 +909,20 @@ asp_status asp_fit_active_set(asp_ctx *c, int64_t idx, const asp_gauss *init,
     if (s != ASP_OK) return s;
     asp_status st = stop_status(c);
     if (st != ASP_OK) { c->phase = 0; return st; }
-    if (rep) {
-        memset(rep, 0, sizeof *rep);
-        rep->n_active = h->n_active;
-        for (int i = 0; i < h->n_active; ++i) rep->members[i] = h->members[i];
-        rep->lm_iters = h->lm_iters;
-        rep->converged = h->converged;
-        rep->used_fallback = h->used_fallback;
-        rep->idx = h->idx;
-        rep->peak = h->peak;
-        rep->chi2_init = h->chi2_init;
-        rep->chi2_final = h->chi2_final;
-        for (int i = 0; i < 4 * h->n_active; ++i) {
-            rep->theta0[i] = h->theta0[i];
-            rep->theta[i] = h->theta[i];
-        }
-        rep->fit_px = h->fit_px;
-        rep->init_source = h->init_source;
-        rep->start_from_proposal = h->start_prop;
-        for (int i = 0; i < 4; ++i) rep->init[i] = h->init[i];
-    }
+    if (rep) fill_report(h, rep);
     c->phase = 2;
     return h->converged ? ASP_OK : ASP_LM_NOT_CONVERGED;
 }
+
+asp_status asp_last_fit(asp_ctx *c, asp_fit_report *rep)
+{
+    if (!c || !rep) return ASP_ERR_INVALID_ARG;
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    fill_report(c->st_host, rep);
+    return ASP_OK;
+}
+
 
 asp_status asp_update_residual(asp_ctx *c, int64_t *pixels_touched)
 {
@@ -955,7 +975,8 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
     const unsigned long long t0 = c->st_host->sum_trials, nc0 = c->st_host->not_converged,
                              fb0 = c->st_host->fallbacks,
                              ep0 = c->st_host->sum_eval_px, gf0 = c->st_host->sum_gram_flops,
-                             sm0 = c->st_host->sum_smoothed, pk0 = c->st_host->pk_tiles_done;
+                             sm0 = c->st_host->sum_smoothed, pk0 = c->st_host->pk_tiles_done,
+                             na0 = c->st_host->not_added;
     const int every = c->opt.refresh_every;
     if (every > 0) {
         s = setup_refresh(c);
@@ -1000,6 +1021,7 @@ asp_status asp_run(asp_ctx *c, int64_t n_iter, asp_run_report *rep)
         rep->gram_flops = (int64_t)(c->st_host->sum_gram_flops - gf0);
         rep->smoothed = (int64_t)(c->st_host->sum_smoothed - sm0);
         rep->peak_tiles_scanned = (int64_t)(c->st_host->pk_tiles_done - pk0);
+        rep->not_added = (int64_t)(c->st_host->not_added - na0);
     }
     return result;
 }
@@ -1582,7 +1604,11 @@ asp_status asp_batch_create(int32_t n_fields, const float *const *dirty, const i
         b->ctx.push_back(c);
     }
     b->grid = asp::batch_grid_size(b->device);
-    if (b->grid < 8) return bail(ASP_ERR_DEVICE);
+    if (b->grid < 8) {
+        fprintf(stderr, "asp_batch_create: the batched kernel's work-groups cannot all be "
+                        "resident at once (private segment or no occupancy)\n");
+        return bail(ASP_ERR_DEVICE);
+    }
     if (!team_ok(b, b->team)) b->team = b->grid / 8;
     // the fields' parameter blocks and the order: largest first
     std::vector<asp::Params> P(n_fields);

@@ -7,7 +7,10 @@ once.  Then:
   * the peak index and the active-set members (in order) must be equal,
   * every member's a and s must agree to 1e-3 relative and x, y to
     1e-3 * max(1, s) pixels,
-  * the residuals must agree to 1e-4 * max|dirty|.
+  * the residuals must agree to 1e-4 * max|dirty|,
+  * both sides must agree on whether the new component joined the list, and
+    the committed lists (old members moved by the loop gain toward their
+    refits, the new component) must agree to the parameter tolerance.
 """
 import numpy as np
 
@@ -59,9 +62,21 @@ class Lockstep:
                "orc_members": orep["members"], "gpu_conv": rep["converged"],
                "orc_conv": orep["converged"], "gpu_theta": rep["theta"],
                "orc_theta": orep["theta"], "resid_err": float(np.abs(R1 - orc.R).max()),
-               "gpu_trials": rep["lm_iters"], "orc_trials": orep["lm_iters"]}
+               "gpu_trials": rep["lm_iters"], "orc_trials": orep["lm_iters"],
+               "added": rep["added"], "orc_added": orep["added"]}
         if rec["members"] == rec["orc_members"]:
             rec["param_err"] = param_errors(rep["theta"], orep["theta"])
+        comps1, ocomps = ctx.components_raw(), orc.comps()
+        rec["n_comps"], rec["orc_n_comps"] = comps1.shape[0], ocomps.shape[0]
+        if comps1.shape == ocomps.shape:
+            # the members this step changed (and the new one): the others are
+            # loaded from the same list and must be identical
+            touched = [j for j in rep["members"][1:]] + list(range(comps0.shape[0], comps1.shape[0]))
+            rec["comp_err"] = param_errors(comps1[touched], ocomps[touched]) if touched else \
+                np.zeros((0, 4))
+            keep = np.ones(comps1.shape[0], bool)
+            keep[touched] = False
+            rec["untouched_equal"] = bool(np.array_equal(comps1[keep], ocomps[keep]))
         self.records.append(rec)
         return rec
 
@@ -69,6 +84,11 @@ class Lockstep:
         assert rec["idx"] == rec["orc_idx"], rec
         assert rec["members"] == rec["orc_members"], rec
         assert rec["resid_err"] <= RESID_TOL * self.peak, (rec["resid_err"], rec["k"])
+        assert rec["added"] == rec["orc_added"], rec
+        assert rec["n_comps"] == rec["orc_n_comps"], rec
+        assert rec["untouched_equal"], rec
         if strict:
+            assert rec["comp_err"].size == 0 or rec["comp_err"].max() <= 1.0, (
+                rec["k"], rec["comp_err"])
             assert rec["param_err"].max() <= 1.0, (rec["k"], rec["param_err"], rec["gpu_theta"],
                                                    rec["orc_theta"])

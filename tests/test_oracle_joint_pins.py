@@ -195,3 +195,80 @@ def test_two_member_lm_optimum_vs_brute_force(orc):
     a1, a2 = chi2(best.x)[1]
     assert c2 == pytest.approx(best.fun, rel=1e-8)
     np.testing.assert_allclose(theta, [[a1, x1, y1, s1], [a2, x2, y2, s2]], atol=2e-6)
+
+
+def test_loop_gain_moves_old_members_toward_their_refit(orc):
+    """Reading of the loop gain (Sect. 3) with an active set: every change of
+    the model is scaled by the gain.  The fit itself does not depend on the
+    gain (pinned above by exact recovery at gain 1); at gain g the new
+    component joins with g times its amplitude and each old member moves the
+    fraction g of the way to its refit; the residual is then the data minus
+    the committed list, by definition."""
+    H = W = 64
+    A = [0.8, 30.3, 31.6, 3.0]
+    B = [0.6, 35.6, 28.4, 2.2]
+    C = [1.0, 31.2, 27.1, 1.6]
+    A0 = np.array([0.72, 30.6, 31.4, 3.15])
+    B0 = np.array([0.66, 35.9, 28.2, 2.3])
+    sky = truncated(H, W, A) + truncated(H, W, B) + truncated(H, W, C)
+    R = sky - truncated(H, W, A0) - truncated(H, W, B0)
+    g = 0.35
+    o = orc.Oracle(R, gain=g, max_iter=10, max_active=5, alpha_b=1.0, omega_b=1.2, lm_tol=1e-10)
+    o.load_state(R, np.array([A0, B0]), 2)
+    rep = o.step()
+    assert rep["members"] == [-1, 1, 0] and rep["added"]
+    np.testing.assert_allclose(rep["theta"], [C, B, A], rtol=1e-10, atol=1e-10)
+    want = [A0 + g * (np.array(A) - A0), B0 + g * (np.array(B) - B0),
+            [g * C[0], C[1], C[2], C[3]]]
+    np.testing.assert_allclose(o.comps(), want, rtol=1e-12, atol=1e-12)
+    expect = sky - sum(truncated(H, W, c) for c in want)
+    assert np.abs(o.R - expect).max() <= 1e-12
+
+
+def test_zero_amplitude_new_component_is_not_added(orc):
+    """An old member that explains the peak: the residual is a Gaussian A
+    minus a stored member at A's width, half its amplitude and 2 px off, less a
+    small beam-sized dip at the peak, which lies 3 px from the stored centre
+    (outside the co-location radius).  The joint fit moves the old member onto
+    A, and the new component would need a negative amplitude: it stays on its
+    sign bound 0.  It is not added: the list keeps one component, now the
+    refit (gain 1), and the residual is the data minus that refit."""
+    H = W = 64
+    wb = 1.2
+    A = [1.0, 30.0, 30.0, 4.0]
+    A0 = [0.5, 32.0, 30.0, 4.0]
+    dip = [0.005, 29.0, 30.0, wb]
+    R = truncated(H, W, A) - truncated(H, W, A0) - truncated(H, W, dip)
+    assert int(np.argmax(np.abs(R))) == 30 * W + 29
+    o = orc.Oracle(R, gain=1.0, max_iter=10, max_active=5, alpha_b=1.0, omega_b=wb)
+    o.load_state(R, np.array([A0]), 1)
+    rep = o.step()
+    assert rep["members"] == [-1, 0]
+    assert rep["theta"][0][0] == 0.0 and not rep["added"]
+    assert o.L == 1 and o.k == 2
+    fit = rep["theta"][1]
+    np.testing.assert_allclose(o.comps()[0], fit, rtol=1e-15, atol=1e-15)
+    np.testing.assert_allclose(fit, A, rtol=0, atol=0.02)
+    expect = R + truncated(H, W, A0) - truncated(H, W, fit)
+    assert np.abs(o.R - expect).max() <= 1e-12
+
+
+def test_field_run_adds_no_zero_amplitude_component(orc):
+    """On the 1024^2 EVLA-like field (seed 1000) the joint fits often leave the
+    new component at zero amplitude, an old member explaining the peak; none
+    of those is added, so no component of the list has amplitude zero and the
+    list is shorter than the iteration count by exactly those iterations."""
+    import skygen
+    f = skygen.make_c1024(1000)
+    ab, wb, _ = orc.psf_fit(f.psf)
+    o = orc.Oracle(f.dirty, gain=f.gain, threshold=f.threshold, max_iter=f.max_iter,
+                   max_active=f.max_active, alpha_b=ab, omega_b=wb)
+    skipped = 0
+    for _ in range(150):
+        rep = o.step()
+        skipped += 0 if rep["added"] else 1
+        assert rep["added"] == (rep["theta"][0][0] != 0.0)
+    assert skipped >= 5
+    assert o.L == 150 - skipped
+    assert np.all(o.comps()[:, 0] != 0.0)
+    assert np.abs(o.residual_from_scratch() - o.R).max() <= 1e-12 * np.abs(f.dirty).max()
