@@ -20,9 +20,20 @@ Besides the throughput the line carries:
                 (8 bytes per pixel read-modify-written); by default the
                 update runs at the end of the fit kernel and is part of its
                 launch time
-  cpu_baseline  the FP64 oracle, single-threaded, continuing the same run
-                from the state at the start of the timed region for a bounded
-                number of seconds
+  peak_cold     the peak search on HBM-cold data (a 1 GiB scrub before each
+                timed launch) and warm (launches back to back), 4 H W bytes
+                per launch against 8 TB/s
+  full_run      every iteration of the workload's configuration (20000 at
+                4096^2) from the dirty image in one asp_run call, its rate and
+                final residual RMS, and the oracle stepped beside the device
+                for a few iterations at the end: per-component errors
+  learned_vs_plain  time to the full run's final residual RMS with the
+                network's start values, from the dirty image, at equal RMS
+                (tracked sum of R^2, first iteration at or below it)
+  cpu_baseline  the FP64 oracle, single-threaded and pinned to one core,
+                continuing the same run from the state at the start of the
+                timed region for a bounded number of seconds; the CPU model
+                and core counts beside it
   smoothing     the smoothing method of initial values with the 5 % switch
                 (init mode 2) on the same field: a full refresh of the
                 smoothed images (every tile, both passes, all trial widths)
@@ -47,6 +58,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -81,86 +93,244 @@ def fit_source_digest() -> str:
     return h.hexdigest()
 
 
-def fit_traffic(workload: str, fit_launches: int):
-    """HBM bytes per fit launch from the committed PMC summary, if it was taken
-    on the current fit kernel sources; else None."""
+def fit_traffic(workload: str, warmup: int, steps: int):
+    """HBM bytes per fit launch from the committed PMC record of this workload,
+    if one was taken over the same timed window (iterations warmup ..
+    warmup + steps) on the current fit kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"k_fit_{workload}_traffic.json")
     try:
         with open(path) as fh:
-            rec = json.load(fh)
+            recs = json.load(fh)
         digest = fit_source_digest()
     except (OSError, ValueError):
         return None
-    if rec.get("fit_sources_sha256") != digest:
-        return None
-    return rec.get("bytes_per_launch")
+    for rec in recs.get("windows", []):
+        if rec.get("warmup") == warmup and rec.get("steps") == steps and \
+                rec.get("fit_sources_sha256") == digest:
+            return rec.get("bytes_per_launch")
+    return None
+
+
+def cpu_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "cpus_allowed": len(os.sched_getaffinity(0))}
 
 
 def cpu_baseline(f, R0, comps0, k0, alpha_b, omega_b, seconds):
-    """The oracle continuing the run from (R0, comps0, k0) for about `seconds`."""
+    """The oracle continuing the run from (R0, comps0, k0) for about `seconds`,
+    on one core: the process is pinned to its first allowed CPU meanwhile."""
     import oracle
-    o = oracle.Oracle(f.dirty, gain=f.gain, threshold=f.threshold, max_iter=f.max_iter,
-                      max_active=f.max_active, cap=f.max_iter + 1, alpha_b=alpha_b,
-                      omega_b=omega_b)
-    o.load_state(R0, comps0, k0)
-    done = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        r = o.step()
-        if r["status"] in (1, 2) or r["status"] < 0:    # a stop or an error; 3 = fit budget used
-            break
-        done += 1
-    secs = time.perf_counter() - t0
+    info = cpu_info()
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[-1]              # the last allowed CPU: away from CPU 0's system work
+    os.sched_setaffinity(0, {core})
+    try:
+        o = oracle.Oracle(f.dirty, gain=f.gain, threshold=f.threshold, max_iter=f.max_iter,
+                          max_active=f.max_active, cap=f.max_iter + 1, alpha_b=alpha_b,
+                          omega_b=omega_b)
+        o.load_state(R0, comps0, k0)
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            r = o.step()
+            if r["status"] in (1, 2) or r["status"] < 0:    # a stop or an error; 3 = fit budget used
+                break
+            done += 1
+        secs = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(allowed))
     return {"value": done / secs if secs > 0 else 0.0, "unit": "iterations/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "pinned_cpu": core, **info,
             "sample": f"{done} iterations ({secs:.1f} s) of the same field continuing from "
                       f"iteration {k0}, the state at the start of the timed region; FP64 C, "
-                      "one thread"}
+                      "one thread, pinned to one core"}
 
 
-def learned_vs_plain(args, f, wpath, rep, secs, rms_plain, torch, asp):
-    """Time to the plain run's residual RMS with the network's start values.
-    A second context warms up plainly over the same iterations, then runs in
-    learned mode in chunks of 100 iterations (an RMS check on the device after
-    each) until its residual RMS is at most the plain run's, or 3x the plain
-    run's iterations have passed."""
+def device_field(f, torch):
+    return torch.from_numpy(f.dirty).cuda(), torch.from_numpy(f.psf).cuda()
+
+
+def tracked_rms(ctx, npx: int) -> float:
+    return math.sqrt(max(ctx.residual_sumsq(tracked=True), 0.0) / npx)
+
+
+def step_errors(ctx, f, o, peak):
+    """One lockstep iteration: the oracle loaded with the context's pre-step
+    state steps once beside it; per-member errors of the fit (a and s
+    relative, x and y in units of max(1, s)) and the residual's max error
+    relative to the dirty image's peak."""
+    import numpy as np
+    R0, comps0, k0 = ctx.residual(), ctx.components_raw(), ctx.counts()[0]
+    rc, idx, val = ctx.find_peak()
+    if rc != 0:
+        return None
+    rc, rep = ctx.fit_active_set(idx)
+    ctx.update_residual()
+    o.load_state(R0, comps0, k0)
+    orep = o.step()
+    out = {"k": int(k0), "same_peak": orep["idx"] == idx,
+           "same_members": orep["members"] == rep["members"], "members": len(rep["members"]),
+           "converged": [bool(rep["converged"]), bool(orep["converged"])],
+           "resid_err_over_peak": float(np.abs(ctx.residual().astype(np.float64) - o.R).max()
+                                        / peak)}
+    if out["same_members"]:
+        g, c = np.asarray(rep["theta"]).reshape(-1, 4), np.asarray(orep["theta"]).reshape(-1, 4)
+        ea = np.abs(g[:, 0] - c[:, 0]) / np.maximum(np.abs(c[:, 0]), 1e-30)
+        es = np.abs(g[:, 3] - c[:, 3]) / c[:, 3]
+        ep = np.maximum(np.abs(g[:, 1] - c[:, 1]), np.abs(g[:, 2] - c[:, 2])) / np.maximum(1.0, c[:, 3])
+        out["per_member"] = [{"amp_rel": float(a), "width_rel": float(w), "pos_over_scale": float(q)}
+                             for a, w, q in zip(ea, es, ep)]
+    return out
+
+
+def full_run_leg(args, f, torch, asp):
+    """The workload's whole run, every iteration of its configuration from the
+    dirty image (20000 at 4096^2), in one asp_run call; then the oracle steps
+    beside the device for a few iterations at the end of the run (lockstep)
+    and the per-component errors of those fits are reported."""
+    import numpy as np
+    import oracle
+    n = f.max_iter
+    d_dirty, d_psf = device_field(f, torch)
+    ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=n + args.full_samples,
+                      max_active=f.max_active)
+    del d_dirty, d_psf
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, rep = ctx.run(n)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    H, W = f.shape
+    rms = tracked_rms(ctx, H * W)
+    out = {"iterations": rep["iterations"], "seconds": secs,
+           "iterations_per_s": rep["iterations"] / secs if secs > 0 else 0.0,
+           "components": rep["components"], "not_added": rep["not_added"],
+           "trials_per_fit": rep["lm_trials"] / max(rep["iterations"], 1),
+           "not_converged": rep["not_converged"], "rms": rms,
+           "rms_dirty": float(np.sqrt(np.mean(f.dirty.astype(np.float64) ** 2)))}
+    log(f"full run {json.dumps(out)}")
+    ab, wb = ctx.psf_gauss()
+    o = oracle.Oracle(f.dirty, gain=f.gain, threshold=f.threshold, max_iter=n + args.full_samples,
+                      max_active=f.max_active, alpha_b=ab, omega_b=wb, cap=n + args.full_samples + 1)
+    peak = float(np.abs(f.dirty).max())
+    samples = []
+    for _ in range(args.full_samples):
+        e = step_errors(ctx, f, o, peak)
+        if e is None:
+            break
+        samples.append(e)
+    out["oracle_lockstep_at_end"] = samples
+    log(f"full run, lockstep at the end {json.dumps(samples)}")
+    ctx.close()
+    return out, rms, secs
+
+
+def learned_equal_rms(args, f, wpath, n_plain, rms_plain, secs_plain, torch, asp):
+    """Time to the plain run's final residual RMS with the network's start
+    values, both from the dirty image.  A search pass runs the learned context
+    in chunks, reading the tracked sum of R^2 after each; in the chunk that
+    crosses the plain RMS it goes back to the chunk's start and steps one
+    iteration at a time, which gives the first iteration N at or below it.  A
+    fresh learned context then runs exactly N iterations in one timed asp_run
+    call (the learned path is deterministic, so it ends at the same RMS)."""
     import numpy as np
     w = np.load(wpath)
-    d_dirty = torch.from_numpy(f.dirty).cuda()
-    d_psf = torch.from_numpy(f.psf).cuda()
-    total = args.warmup + 3 * args.steps
-    ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=max(f.max_iter, total),
-                      max_active=f.max_active, fit_solo_tiles=args.solo_tiles,
-                      fit_min_tiles=args.min_tiles)
-    del d_dirty, d_psf
-    ctx.set_mlp(w)
-    ctx.run(args.warmup)
-    ctx.set_init_mode(1)
-    torch.cuda.synchronize()
-    done, trials, fallbacks, t_learned = 0, 0, 0, 0.0
-    rms = ctx.residual_rms()
-    reached = False
-    while done < 3 * rep["iterations"]:
-        t0 = time.perf_counter()
-        rc, r = ctx.run(100)
-        torch.cuda.synchronize()
-        t_learned += time.perf_counter() - t0
-        done += r["iterations"]
-        trials += r["lm_trials"]
-        fallbacks += r["fallbacks"]
-        rms = ctx.residual_rms()
-        if rms <= rms_plain or r["iterations"] == 0:
-            reached = rms <= rms_plain
+    H, W = f.shape
+    cap = 2 * n_plain
+    d_dirty, d_psf = device_field(f, torch)
+
+    def learned_ctx():
+        c = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=cap, max_active=f.max_active)
+        c.set_mlp(w)
+        c.set_init_mode(1)
+        return c
+
+    ctx = learned_ctx()
+    N, chunk = None, 512
+    while ctx.counts()[0] < cap:
+        blob = ctx.save_state()
+        k0 = ctx.counts()[0]
+        rc, r = ctx.run(min(chunk, cap - k0))
+        if tracked_rms(ctx, H * W) <= rms_plain:
+            ctx.load_state(blob)
+            while ctx.counts()[0] < cap:
+                ctx.run(1)
+                if tracked_rms(ctx, H * W) <= rms_plain:
+                    N = ctx.counts()[0]
+                    break
             break
+        if r["iterations"] == 0:
+            break
+    rms_cap = tracked_rms(ctx, H * W)
     ctx.close()
     out = {"weights": os.path.basename(wpath),
-           "plain": {"iterations": rep["iterations"], "seconds": secs, "rms": rms_plain,
-                     "trials_per_fit": rep["lm_trials"] / max(rep["iterations"], 1)},
-           "learned": {"iterations": done, "seconds": t_learned, "rms": rms,
-                       "trials_per_fit": trials / max(done, 1), "fallbacks": fallbacks},
-           "reached_plain_rms": reached,
-           "time_ratio_learned_over_plain": (t_learned / secs) if reached and secs > 0 else None}
-    log(f"learned vs plain {json.dumps(out)}")
+           "plain": {"iterations": n_plain, "seconds": secs_plain, "rms": rms_plain},
+           "reached_plain_rms": N is not None, "iteration_cap": cap}
+    if N is None:
+        out["learned"] = {"iterations": cap, "rms": rms_cap}
+    else:
+        ctx = learned_ctx()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, r = ctx.run(N)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out["learned"] = {"iterations": r["iterations"], "seconds": t,
+                          "rms": tracked_rms(ctx, H * W),
+                          "trials_per_fit": r["lm_trials"] / max(r["iterations"], 1),
+                          "fallbacks": r["fallbacks"],
+                          "fallback_rate": r["fallbacks"] / max(r["iterations"], 1),
+                          "not_added": r["not_added"], "components": r["components"]}
+        out["time_ratio_learned_over_plain"] = t / secs_plain if secs_plain > 0 else None
+        ctx.close()
+    del d_dirty, d_psf
+    log(f"learned vs plain at equal RMS {json.dumps(out)}")
+    return out
+
+
+def cold_peak_leg(args, f, torch, asp, reps: int = 20):
+    """The peak search on HBM-cold data: before each timed launch a 1 GiB
+    buffer is read and written (four times the 256 MB Infinity Cache and all
+    of L2), so the 4 H W bytes of the scan come from HBM.  The same launches
+    back to back give the warm (cache-resident) rate.  HIP events on the
+    context's stream."""
+    H, W = f.shape
+    d_dirty, d_psf = device_field(f, torch)
+    ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=f.max_iter,
+                      max_active=f.max_active)
+    del d_dirty, d_psf
+    scrub = torch.zeros(256 << 20, dtype=torch.float32, device="cuda")
+    ctx.kernel_timing(True)
+    ctx.find_peak()
+    m0, n0 = ctx.kernel_times()["peak"]
+    for _ in range(reps):
+        scrub.add_(1.0)
+        torch.cuda.synchronize()
+        ctx.find_peak()
+    m1, n1 = ctx.kernel_times()["peak"]
+    for _ in range(reps):
+        ctx.find_peak()
+    m2, n2 = ctx.kernel_times()["peak"]
+    ctx.close()
+    del scrub
+    b = 4.0 * H * W
+    cold_us = (m1 - m0) / max(n1 - n0, 1) * 1e3
+    warm_us = (m2 - m1) / max(n2 - n1, 1) * 1e3
+    out = {"bytes_per_launch": b, "launches": n1 - n0, "scrub_bytes": 4 * (256 << 20),
+           "cold": {"avg_launch_us": cold_us, "achieved_gbs": b / cold_us / 1e3,
+                    "frac": b / cold_us / 1e3 / PEAK_HBM_GBS},
+           "warm": {"avg_launch_us": warm_us, "achieved_gbs": b / warm_us / 1e3,
+                    "frac": b / warm_us / 1e3 / PEAK_HBM_GBS}}
+    log(f"peak search cold/warm {json.dumps(out)}")
     return out
 
 
@@ -563,6 +733,14 @@ def main():
                     help="only run a plain 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-versus-plain start comparison")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="skip the whole-configuration run (and the learned comparison)")
+    ap.add_argument("--full-samples", type=int, default=4,
+                    help="oracle lockstep iterations at the end of the whole run")
+    ap.add_argument("--no-cold-peak", action="store_true",
+                    help="skip the cold-cache peak search")
+    ap.add_argument("--only", default=None, choices=("cold_peak", "update_large", "full_run"),
+                    help="run one auxiliary leg alone (for profiling), no JSON line")
     ap.add_argument("--weights", default=None, help="proposal network weights (.npy)")
     ap.add_argument("--no-smoothing", action="store_true",
                     help="skip the smoothing-method (init mode 2) leg")
@@ -611,6 +789,12 @@ def main():
     H, W = f.shape
     log(f"generated {f.name} {f.shape} in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
+    if args.only:
+        fn = {"cold_peak": lambda: cold_peak_leg(args, f, torch, asp),
+              "update_large": lambda: update_large_leg(args, f, torch, asp),
+              "full_run": lambda: full_run_leg(args, f, torch, asp)[0]}[args.only]
+        fn()
+        return
     d_dirty = torch.from_numpy(f.dirty).cuda()
     d_psf = torch.from_numpy(f.psf).cuda()
     total = args.warmup + args.steps
@@ -656,7 +840,7 @@ def main():
             avg_s = fit_ms / fit_n * 1e-3
             flops_per_launch = rep["gram_flops"] / fit_n
             achieved = flops_per_launch / avg_s / 1e12
-            tr = fit_traffic(args.workload, fit_n)
+            tr = fit_traffic(args.workload, args.warmup, done)
             roofline = {"kernel": "k_fit", "bound": "alu", "achieved": achieved,
                         "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                         "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": tr,
@@ -680,10 +864,18 @@ def main():
                                "bytes_per_iteration": 8.0 * rep["pixels_updated"] / max(done, 1)}
 
     rms_plain = ctx.residual_rms()
-    learned = None
-    wpath = args.weights or os.path.join(ROOT, "paper_1606_07872_amd", "proposal_weights.npy")
-    if not args.no_learned and os.path.exists(wpath):
-        learned = learned_vs_plain(args, f, wpath, rep, secs, rms_plain, torch, asp)
+
+    cold_peak = None
+    if not args.no_cold_peak and not args.no_kernel_events:
+        cold_peak = cold_peak_leg(args, f, torch, asp)
+
+    full_run, learned = None, None
+    if not args.no_full_run:
+        full_run, rms_full, secs_full = full_run_leg(args, f, torch, asp)
+        wpath = args.weights or os.path.join(ROOT, "paper_1606_07872_amd", "proposal_weights.npy")
+        if not args.no_learned and os.path.exists(wpath):
+            learned = learned_equal_rms(args, f, wpath, full_run["iterations"], rms_full,
+                                        secs_full, torch, asp)
 
     peak_tiles = None
     if not args.no_peak_tiles:
@@ -730,6 +922,8 @@ def main():
                    "kernel_events": not args.no_kernel_events},
         "roofline": roofline,
         "hbm": hbm,
+        "peak_cold": cold_peak,
+        "full_run": full_run,
         "learned_vs_plain": learned,
         "smoothing": smoothing,
         "peak_tiles": peak_tiles,

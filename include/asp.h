@@ -231,6 +231,23 @@ asp_status asp_fit_active_set(asp_ctx *ctx, int64_t idx, const asp_gauss *init,
 asp_status asp_update_residual(asp_ctx *ctx, int64_t *pixels_touched);
 
 /*
+ * One evaluation of the fit objective on the device, the LM trial's own code
+ * path (diagnostic; Sect. 3, Eq. 4 over the union U of the members' windows):
+ * the m members' parameters theta (4 m doubles, (a, x, y, s), the new
+ * component first) are evaluated against the context's residual with the
+ * old members' stored Gaussians, stored[4 j .. 4 j + 3] for j >= 1, added
+ * back on their stored windows (stored may be NULL when m = 1; stored[0..3]
+ * is not read).  Outputs (host, each nullable): jtj = J^T J (n x n, n = 4 m,
+ * row-major), jtr = J^T (D - M) (n), F = sum_U M (M - 2 D), chi2 =
+ * sum_U (D - M)^2, npx = |U|.  Nothing of the context changes.  Returns
+ * ASP_ERR_INVALID_ARG for m outside 1..ASP_MAX_ACTIVE or non-finite
+ * parameters or widths that are not positive, ASP_ERR_STATE inside a
+ * step-API sequence.
+ */
+asp_status asp_eval_trial(asp_ctx *ctx, int32_t m, const double *theta, const double *stored,
+                          double *jtj, double *jtr, double *F, double *chi2, int64_t *npx);
+
+/*
  * The report of the last fit made by any path (the step API, asp_step,
  * asp_run or a batched launch), read from the device state.  rep must not be
  * NULL.

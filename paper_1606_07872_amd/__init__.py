@@ -23,7 +23,7 @@ MAX_SCALES = 8
 # Every symbol include/asp.h declares.
 EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destroy",
            "asp_last_error", "asp_find_peak", "asp_fit_active_set", "asp_update_residual",
-           "asp_last_fit",
+           "asp_last_fit", "asp_eval_trial",
            "asp_step", "asp_run", "asp_components", "asp_components_raw", "asp_residual",
            "asp_residual_device", "asp_psf_gauss", "asp_counts", "asp_fit_profile",
            "asp_kernel_timing", "asp_kernel_times", "asp_set_mlp", "asp_set_init_mode",
@@ -139,6 +139,7 @@ def lib():
         L.asp_fit_active_set.argtypes = [vp, i64, P(Gauss), P(FitReport)]
         L.asp_update_residual.argtypes = [vp, P(i64)]
         L.asp_last_fit.argtypes = [vp, P(FitReport)]
+        L.asp_eval_trial.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, P(f64), P(f64), P(i64)]
         L.asp_step.argtypes = [vp]
         L.asp_run.argtypes = [vp, i64, P(RunReport)]
         L.asp_components.argtypes = [vp, vp, i64, P(i64)]
@@ -283,6 +284,23 @@ class Context:
         rep = FitReport()
         self._check(lib().asp_last_fit(self._ctx, ctypes.byref(rep)))
         return report_dict(rep)
+
+    def eval_trial(self, theta, stored=None) -> dict:
+        """One evaluation of the fit objective on the device (asp_eval_trial):
+        theta (m, 4), stored (m, 4) with row 0 unused.  Returns F, H = J^T J,
+        g = J^T (D - M), chi2 and the pixel count of U."""
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, 4))
+        m = th.shape[0]
+        sd = np.zeros_like(th) if stored is None else np.ascontiguousarray(
+            np.asarray(stored, dtype=np.float64).reshape(m, 4))
+        n = 4 * m
+        H = np.zeros((n, n))
+        g = np.zeros(n)
+        F, chi2, npx = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        self._check(lib().asp_eval_trial(self._ctx, m, th.ctypes.data, sd.ctypes.data,
+                                         H.ctypes.data, g.ctypes.data, ctypes.byref(F),
+                                         ctypes.byref(chi2), ctypes.byref(npx)))
+        return {"F": F.value, "H": H, "g": g, "chi2": chi2.value, "npx": int(npx.value)}
 
     def update_residual(self) -> int:
         n = ctypes.c_int64()

@@ -105,6 +105,12 @@ struct DevState {
     // pixels rewritten by the updates, one running count per update
     // work-group index (no two work-groups add to one counter)
     unsigned long long *px_slots;
+    // one evaluation of a given trial (asp_eval_trial): diag_m > 0 members,
+    // their parameters and the old members' stored ones; the reduced sums go
+    // to diag_out: J^T J (n x n), J^T r (n), F, chi2, the pixel count
+    int32_t diag_m, pad_d;
+    double diag_theta[kMaxN], diag_stored[kMaxN];
+    double *diag_out;
 };
 constexpr int kSqSlots = 4096;
 

@@ -39,8 +39,10 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
+// The work-group's key goes to slots[rank % kPeakSlots] (a 64-bit atomicMax);
+// the peak is the maximum over the kPeakSlots slots.
 __device__ inline void peak_scan(const float *__restrict__ R, int64_t n, uint32_t rank,
-                                 uint32_t size, DevState *st)
+                                 uint32_t size, unsigned long long *slots)
 {
     const uint32_t n4 = (uint32_t)(n >> 2);
     const float4 *R4 = reinterpret_cast<const float4 *>(R);
@@ -73,7 +75,7 @@ __device__ inline void peak_scan(const float *__restrict__ R, int64_t n, uint32_
     if (threadIdx.x == 0) {
         unsigned long long k = wk[0];
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) k = wk[w] > k ? wk[w] : k;
-        atomicMax(&st->peak_keys[rank % kPeakSlots], k);
+        atomicMax(&slots[rank % kPeakSlots], k);
     }
 }
 

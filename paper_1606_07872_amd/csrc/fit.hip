@@ -1185,6 +1185,58 @@ __device__ __forceinline__ void fit_begin(const Params &p, WGShared &S, bool abo
     if (S.stop) st->stop = S.stop;
 }
 
+// One evaluation of the trial at S.th_e (old members at S.th_old) by the
+// leading work-group: F, chi2, the pixel count and [J r]^T [J r] reduced into
+// S.Fe, S.chi2e, S.npx_e, S.ge and the Gram buffer H2 + (1 - S.hsel) n^2.  A
+// trial larger than p.solo_tiles tiles is published (with G->cmd = cmd when
+// cmd != 0) and shared by the nwg work-groups.  Returns false when a wait ran
+// out; the context is then marked with ASP_ERR_DEVICE.
+__device__ __forceinline__ bool trial_eval(const Params &p, FitGlobal *G, WGShared &S, float *tile,
+                                           double *red, double *H2, int nwg, int cmd)
+{
+    DevState *st = p.st;
+    const int t = threadIdx.x;
+    const int ngroups = (nwg + p.group - 1) / p.group;
+    prepare(p, S, S.m, S.th_e, S.th_old);
+    const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
+    lap(p, S, kPPrepare);
+    double *He = H2 + (1 - S.hsel) * (kMaxN * kMaxN);   // the trial's buffer
+    if (ntiles <= p.solo_tiles) {
+        // small: the leading work-group alone, no publication
+        evaluate_row(p, S, tile, red, 0, 1, p.partials);
+        lap(p, S, kPEval);
+        reduce_partials(p, S, 0, 1, He);
+        lap(p, S, kPReduce);
+        return true;
+    }
+    // large: every work-group takes a share
+    const int geff = eval_groups(ntiles, nwg, p.min_tiles);
+    const int ng_eval = (geff + p.group - 1) / p.group;
+    if (t < S.n) G->th_e[t] = S.th_e[t];
+    if (t == 0 && cmd) G->cmd = cmd;
+    publish(G);
+    evaluate_row(p, S, tile, red, 0, geff, p.partials);
+    lap(p, S, kPEval);
+    arrive(p, G, S, 0, nwg, geff, false);
+    lap(p, S, kPArrive);
+    if (t == 0) {
+        // the rows are read with atomic loads: no acquire
+        S.abort = spin_until(&G->top, (unsigned)ngroups, p.spin_ticks, false) ? 0 : 1;
+        __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    lap(p, S, kPWait);
+    __syncthreads();
+    if (S.abort) {
+        if (t == 0) st->stop = ASP_ERR_DEVICE;
+        __syncthreads();
+        return false;
+    }
+    if (ng_eval > 1) reduce_partials(p, S, nwg, nwg + ng_eval, He);
+    else reduce_partials(p, S, 0, geff, He);
+    lap(p, S, kPReduce);
+    return true;
+}
+
 // Start values, active set, the LM trials and the commit of one fit, by the
 // leading work-group (share 0 of nwg).  A trial larger than p.solo_tiles tiles
 // is published (with G->cmd = cmd when cmd != 0) and shared by the nwg
@@ -1196,49 +1248,11 @@ __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShar
 {
     DevState *st = p.st;
     const int t = threadIdx.x;
-    const int ngroups = (nwg + p.group - 1) / p.group;
     mark(S);
     setup_fit(p, G, S, S.use_prop != 0);
     lap(p, S, kPSetup);
     for (;;) {
-        // the trial at S.th_e
-        prepare(p, S, S.m, S.th_e, S.th_old);
-        const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
-        lap(p, S, kPPrepare);
-        if (ntiles <= p.solo_tiles) {
-            // small: the leading work-group alone, no publication
-            evaluate_row(p, S, tile, red, 0, 1, p.partials);
-            lap(p, S, kPEval);
-            reduce_partials(p, S, 0, 1, H2 + (1 - S.hsel) * (kMaxN * kMaxN));
-            lap(p, S, kPReduce);
-        } else {
-            // large: every work-group takes a share
-            const int geff = eval_groups(ntiles, nwg, p.min_tiles);
-            const int ng_eval = (geff + p.group - 1) / p.group;
-            if (t < S.n) G->th_e[t] = S.th_e[t];
-            if (t == 0 && cmd) G->cmd = cmd;
-            publish(G);
-            evaluate_row(p, S, tile, red, 0, geff, p.partials);
-            lap(p, S, kPEval);
-            arrive(p, G, S, 0, nwg, geff, false);
-            lap(p, S, kPArrive);
-            if (t == 0) {
-                // the rows are read with atomic loads: no acquire
-                S.abort = spin_until(&G->top, (unsigned)ngroups, p.spin_ticks, false) ? 0 : 1;
-                __hip_atomic_store(&G->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            lap(p, S, kPWait);
-            __syncthreads();
-            if (S.abort) {
-                if (t == 0) st->stop = ASP_ERR_DEVICE;
-                __syncthreads();
-                return false;
-            }
-            double *He = H2 + (1 - S.hsel) * (kMaxN * kMaxN);   // the trial's buffer
-            if (ng_eval > 1) reduce_partials(p, S, nwg, nwg + ng_eval, He);
-            else reduce_partials(p, S, 0, geff, He);
-            lap(p, S, kPReduce);
-        }
+        if (!trial_eval(p, G, S, tile, red, H2, nwg, cmd)) return false;
         lm_step(p, S, H2, A);
         lap(p, S, kPLmStep);
         if (t == 0) {
@@ -1281,9 +1295,9 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
     const int t = threadIdx.x;
     const int wg = blockIdx.x, nwg = gridDim.x;
 
-    // Nothing writes the stop flag before every work-group has checked in, so
-    // all of them agree here.
-    if (st->stop) return;
+    // Nothing writes the stop flag (or the evaluation request) before every
+    // work-group has checked in, so all of them agree here.
+    if (st->stop && st->diag_m == 0) return;
 
     mark(S);
     // Check in: every work-group reads the generation before work-group 0 may
@@ -1336,6 +1350,45 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
         lap(p, S, kPCheckin);
     }
     __syncthreads();
+    if (st->diag_m > 0) {
+        // one evaluation of a given trial (asp_eval_trial): no peak, no LM
+        // step, no commit
+        if (t == 0) {
+            S.m = st->diag_m;
+            S.n = 4 * S.m;
+            S.hsel = 0;
+            G->m = S.m;
+            G->n = S.n;
+            G->done = 0;
+        }
+        __syncthreads();
+        if (t < S.n) {
+            S.th_e[t] = st->diag_theta[t];
+            S.th_old[t] = st->diag_stored[t];
+            G->th_old[t] = S.th_old[t];
+        }
+        __syncthreads();
+        const bool ok = !S.abort && trial_eval(p, G, S, tile, red, H2, nwg, 0);
+        const int n = S.n;
+        double *o = st->diag_out;
+        if (ok) {
+            const double *He = H2 + kMaxN * kMaxN;        // 1 - hsel
+            for (int e = t; e < n * n; e += kT) o[e] = He[e];
+            if (t < n) o[n * n + t] = S.ge[t];
+            if (t == 0) {
+                o[n * n + n] = S.Fe;
+                o[n * n + n + 1] = S.chi2e;
+                o[n * n + n + 2] = (double)S.npx_e;
+            }
+        }
+        if (t == 0) {
+            if (!ok) st->stop = ASP_ERR_DEVICE;
+            st->diag_m = 0;
+            G->done = 1;
+        }
+        publish(G);
+        return;
+    }
     collect_peak_key(st, true, &S.key);
     if (t == 0) {
         fit_begin(p, S, S.abort != 0);
@@ -1448,7 +1501,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
             }
             int geff = 0;
             if (cmd == kCmdPeak) {
-                peak_scan(P.R, P.H * P.W, (uint32_t)rank, (uint32_t)T, P.st);
+                peak_scan(P.R, P.H * P.W, (uint32_t)rank, (uint32_t)T, P.st->peak_keys);
             } else if (cmd == kCmdUpdate) {
                 update_tiles(P, rank, T);
             } else if (cmd == kCmdEval) {
@@ -1494,11 +1547,11 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
             // the peak of |R| (Sect. 2 step 1)
             const int64_t npx = P.H * P.W;
             if (T == 1 || npx <= b.solo_peak_px) {
-                peak_scan(P.R, npx, 0u, 1u, P.st);
+                peak_scan(P.R, npx, 0u, 1u, P.st->peak_keys);
             } else {
                 if (t == 0) G->cmd = kCmdPeak;
                 publish(G);
-                peak_scan(P.R, npx, 0u, (uint32_t)T, P.st);
+                peak_scan(P.R, npx, 0u, (uint32_t)T, P.st->peak_keys);
                 arrive(P, G, S, 0, T, 0);
                 if (!team_wait(G, S, ngroups, b.spin_ticks)) { ok = false; break; }
             }

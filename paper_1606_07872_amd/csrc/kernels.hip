@@ -15,7 +15,7 @@ __global__ __launch_bounds__(256) void k_peak(const float *__restrict__ R, int64
                                               DevState *st)
 {
     if (st->stop) return;
-    peak_scan(R, n, blockIdx.x, gridDim.x, st);
+    peak_scan(R, n, blockIdx.x, gridDim.x, st->peak_keys);
 }
 
 hipError_t launch_peak(const Params &p, int grid, hipStream_t s)

@@ -34,6 +34,7 @@ struct asp_ctx {
     asp_component *comp_out = nullptr;
     asp::FitGlobal *fg = nullptr;
     double *partials = nullptr;
+    double *diag_out = nullptr;           // asp_eval_trial's reduced sums (first use)
     Params P{};
     int peak_grid = 1024, update_grid = 1024;
     int phase = 0;                        // 0 ready, 1 peak found, 2 fitted
@@ -115,6 +116,7 @@ void release(asp_ctx *c)
     (void)hipFree(c->c_added); (void)hipFree(c->c_updated);
     (void)hipFree(c->st); (void)hipFree(c->work); (void)hipFree(c->comp_out);
     (void)hipFree(c->fg); (void)hipFree(c->partials); (void)hipFree(c->net);
+    (void)hipFree(c->diag_out);
     (void)hipFree(c->sumsq);
     (void)hipFree(c->sq_slots);
     (void)hipFree(c->px_slots);
@@ -863,14 +865,19 @@ const char *asp_last_error(const asp_ctx *ctx)
 asp_status asp_find_peak(asp_ctx *c, int64_t *idx, float *value)
 {
     if (!c) return ASP_ERR_INVALID_ARG;
-    if (c->pk_tiles) HIP_OR_FAIL(c, asp::launch_peak_tiles(c->P, c->pk_tiles, c->stream));
-    else HIP_OR_FAIL(c, asp::launch_peak(c->P, c->peak_grid, c->stream));
+    asp_status ts = timed(c, 0, [&] {
+        return c->pk_tiles ? asp::launch_peak_tiles(c->P, c->pk_tiles, c->stream)
+                           : asp::launch_peak(c->P, c->peak_grid, c->stream);
+    });
+    if (ts != ASP_OK) return ts;
     HIP_OR_FAIL(c, asp::launch_peak_decode(c->P, c->stream));
     if (c->P.smooth) {
         HIP_OR_FAIL(c, asp::launch_smooth_passes(c->P, 0, c->stream));
         HIP_OR_FAIL(c, asp::launch_smooth_pick(c->P, 0, c->stream));
     }
     asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    s = harvest(c);
     if (s != ASP_OK) return s;
     if (idx) *idx = c->st_host->idx;
     if (value) *value = c->st_host->peak;
@@ -912,6 +919,51 @@ asp_status asp_fit_active_set(asp_ctx *c, int64_t idx, const asp_gauss *init,
     if (rep) fill_report(h, rep);
     c->phase = 2;
     return h->converged ? ASP_OK : ASP_LM_NOT_CONVERGED;
+}
+
+asp_status asp_eval_trial(asp_ctx *c, int32_t m, const double *theta, const double *stored,
+                          double *jtj, double *jtr, double *F, double *chi2, int64_t *npx)
+{
+    if (!c || m < 1 || m > ASP_MAX_ACTIVE || !theta || (m > 1 && !stored))
+        return ASP_ERR_INVALID_ARG;
+    if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_eval_trial inside a step-API sequence");
+    for (int i = 0; i < 4 * m; ++i)
+        if (!isfinite(theta[i]) || (i >= 4 && !isfinite(stored[i])))
+            return fail(c, ASP_ERR_INVALID_ARG, "non-finite trial parameters");
+    for (int j = 0; j < m; ++j)
+        if (!(theta[4 * j + 3] > 0.0) || (j > 0 && !(stored[4 * j + 3] > 0.0)))
+            return fail(c, ASP_ERR_INVALID_ARG, "widths must be positive");
+    const int n = 4 * m;
+    const size_t nout = (size_t)asp::kMaxN * asp::kMaxN + asp::kMaxN + 3;
+    if (!c->diag_out) HIP_OR_FAIL(c, dev_alloc(&c->diag_out, nout));
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    DevState *h = c->st_host;
+    const int32_t stop0 = h->stop;
+    h->diag_m = m;
+    for (int i = 0; i < asp::kMaxN; ++i) {
+        h->diag_theta[i] = i < n ? theta[i] : 0.0;
+        h->diag_stored[i] = (i >= 4 && i < n) ? stored[i] : 0.0;
+    }
+    h->diag_out = c->diag_out;
+    HIP_OR_FAIL(c, hipMemcpyAsync((char *)c->st + offsetof(DevState, diag_m), &h->diag_m,
+                                  sizeof(DevState) - offsetof(DevState, diag_m),
+                                  hipMemcpyHostToDevice, c->stream));
+    asp::Params q = c->P;
+    q.fuse_update = 0;
+    HIP_OR_FAIL(c, asp::launch_fit(q, c->stream));
+    std::vector<double> out((size_t)n * n + n + 3);
+    HIP_OR_FAIL(c, hipMemcpyAsync(out.data(), c->diag_out, sizeof(double) * out.size(),
+                                  hipMemcpyDeviceToHost, c->stream));
+    s = pull_all(c);
+    if (s != ASP_OK) return s;
+    if (h->stop != stop0) return fail(c, ASP_ERR_DEVICE, "the evaluation's waits ran out");
+    if (jtj) memcpy(jtj, out.data(), sizeof(double) * n * n);
+    if (jtr) memcpy(jtr, out.data() + n * n, sizeof(double) * n);
+    if (F) *F = out[n * n + n];
+    if (chi2) *chi2 = out[n * n + n + 1];
+    if (npx) *npx = (int64_t)out[n * n + n + 2];
+    return ASP_OK;
 }
 
 asp_status asp_last_fit(asp_ctx *c, asp_fit_report *rep)

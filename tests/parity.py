@@ -18,6 +18,17 @@ import oracle
 
 PARAM_RTOL = 1e-3
 RESID_TOL = 1e-4
+# Several correct results: when the fit's J^T J (scaled to unit diagonal) has a
+# condition number above this, its members are not individually determined
+# and only their sum -- the residual -- is compared.
+COND_MAX = 1e8
+
+
+def scaled_cond(H) -> float:
+    """Condition number of J^T J scaled to unit diagonal (unit-free)."""
+    H = np.asarray(H, dtype=np.float64)
+    d = np.sqrt(np.maximum(np.diag(H), 1e-300))
+    return float(np.linalg.cond(H / np.outer(d, d)))
 
 
 def param_errors(gpu_theta, orc_theta):
@@ -51,7 +62,7 @@ class Lockstep:
         k0, _ = ctx.counts()
         rc, idx, val = ctx.find_peak()
         orc.load_state(R0, comps0, k0)
-        orep = orc.step(init=init)
+        orep = orc.step(init=init, want_hess=True)
         if rc != 0:
             assert orep["status"] == rc, (rc, orep["status"])
             return None
@@ -63,7 +74,8 @@ class Lockstep:
                "orc_conv": orep["converged"], "gpu_theta": rep["theta"],
                "orc_theta": orep["theta"], "resid_err": float(np.abs(R1 - orc.R).max()),
                "gpu_trials": rep["lm_iters"], "orc_trials": orep["lm_iters"],
-               "added": rep["added"], "orc_added": orep["added"]}
+               "added": rep["added"], "orc_added": orep["added"],
+               "cond": scaled_cond(orep["hess"]) if "hess" in orep else 0.0}
         if rec["members"] == rec["orc_members"]:
             rec["param_err"] = param_errors(rep["theta"], orep["theta"])
         comps1, ocomps = ctx.components_raw(), orc.comps()
@@ -87,7 +99,7 @@ class Lockstep:
         assert rec["added"] == rec["orc_added"], rec
         assert rec["n_comps"] == rec["orc_n_comps"], rec
         assert rec["untouched_equal"], rec
-        if strict:
+        if strict and rec["cond"] <= COND_MAX:
             assert rec["comp_err"].size == 0 or rec["comp_err"].max() <= 1.0, (
                 rec["k"], rec["comp_err"])
             assert rec["param_err"].max() <= 1.0, (rec["k"], rec["param_err"], rec["gpu_theta"],

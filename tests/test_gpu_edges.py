@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import skygen
-from parity import Lockstep, RESID_TOL, param_errors
+from parity import COND_MAX, scaled_cond, Lockstep, RESID_TOL, param_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -125,20 +125,23 @@ def test_lockstep_largest_active_set():
         rc, rep = ctx.fit_active_set(idx)
         ctx.update_residual()
         orc.load_state(R0, comps0, k0)
-        orep = orc.step()
+        orep = orc.step(want_hess=True)
         assert orep["idx"] == idx and orep["members"] == rep["members"], it
         m_max = max(m_max, rep["n_active"])
+        cond = scaled_cond(orep["hess"])
         R1 = ctx.residual().astype(np.float64)
         err = float(np.abs(R1 - orc.R).max())
         pe = param_errors(rep["theta"], orep["theta"]).max()
         print(f"iteration {k0}: m {rep['n_active']} converged {rep['converged']}/"
               f"{orep['converged']} trials {rep['lm_iters']}/{orep['lm_iters']} added "
               f"{rep['added']}/{orep['added']} param err/tol {pe:.3g} resid err/tol "
-              f"{err / (RESID_TOL * peak):.3g}", flush=True)
+              f"{err / (RESID_TOL * peak):.3g} cond {cond:.3g}", flush=True)
         assert rep["added"] == orep["added"], it
         if rep["converged"] and orep["converged"]:
             assert err <= RESID_TOL * peak, it
-            assert pe <= 1.0, it
+            # an ill-conditioned joint fit determines the members' sum, not
+            # each member: then the residual alone is compared
+            assert pe <= 1.0 or cond > COND_MAX, it
             n_strict += 1
         else:
             # a fit that used its whole budget on both sides stops at different

@@ -34,6 +34,8 @@ def test_free_run_against_the_oracle(case):
     g = float(np.float32(f.gain))
     orc = oracle.Oracle(f.dirty, gain=g, threshold=float(np.float32(f.threshold)),
                         max_iter=n_iter, max_active=f.max_active, alpha_b=ab, omega_b=wb)
+    dirty_peak = float(np.abs(f.dirty).max())
+    small = f.dirty.size <= 1 << 20          # residuals compared after every iteration
     gpu, cpu = [], []
     for _ in range(n_iter):
         rc, idx, _ = ctx.find_peak()
@@ -41,28 +43,38 @@ def test_free_run_against_the_oracle(case):
             break
         _, rep = ctx.fit_active_set(idx)
         ctx.update_residual()
+        R = ctx.residual().astype(np.float64) if small else None
         gpu.append((idx, tuple(rep["members"]), np.asarray(rep["theta"]), rep["converged"],
-                    float(rep["peak"])))
+                    float(rep["peak"]), R))
     for _ in range(n_iter):
         r = orc.step()
         if r["status"] not in (oracle.ORC_OK, oracle.ORC_LM_NOT_CONVERGED):
             break
         cpu.append((r["idx"], tuple(r["members"]), r["theta"].ravel(), r["converged"],
-                    float(r["peak"])))
+                    float(r["peak"]), orc.R.copy() if small else None))
     n = min(len(gpu), len(cpu))
     first = next((i for i in range(n) if gpu[i][:2] != cpu[i][:2]), n)
-    dirty_peak = float(np.abs(f.dirty).max())
+    for i in range(first):
+        if gpu[i][3] and cpu[i][3]:
+            assert param_errors(gpu[i][2], cpu[i][2]).max() <= 1.0, i
+    if small:
+        # the first iteration after which the residuals differ by more than
+        # the lockstep tolerance: the runs may part there only through a fit
+        # that used its whole budget on one side (its end point is not
+        # determined), never after two converged fits
+        part = next((i for i in range(first) if np.abs(gpu[i][5] - cpu[i][5]).max() >
+                     1e-4 * dirty_peak), first)
+        if part < first:
+            print(f"{case}: residuals part after iteration {part}, converged "
+                  f"{gpu[part][3]}/{cpu[part][3]}", flush=True)
+            assert not (gpu[part][3] and cpu[part][3]), part
+        elif first < n and gpu[first][0] != cpu[first][0]:
+            # with equal residuals the peaks part only at a near tie
+            assert abs(abs(gpu[first][4]) - abs(cpu[first][4])) <= 1e-4 * dirty_peak, first
     if first < n:
         print(f"{case}: at iteration {first} the GPU fits pixel {gpu[first][0]} (|R| "
               f"{abs(gpu[first][4]):.7g}) with members {gpu[first][1]}, the oracle pixel "
               f"{cpu[first][0]} (|R| {abs(cpu[first][4]):.7g}) with {cpu[first][1]}", flush=True)
-        if gpu[first][0] != cpu[first][0]:
-            # the runs part at a near tie of two maxima of |R| (FP32 against
-            # FP64 residuals), not at a wrong peak
-            assert abs(abs(gpu[first][4]) - abs(cpu[first][4])) <= 1e-4 * dirty_peak, first
-    for i in range(first):
-        if gpu[i][3] and cpu[i][3]:
-            assert param_errors(gpu[i][2], cpu[i][2]).max() <= 1.0, i
     R = ctx.residual().astype(np.float64)
     rms_g, rms_c = float(np.sqrt(np.mean(R ** 2))), float(np.sqrt(np.mean(orc.R ** 2)))
     flux_g = float(sum(c["flux"] for c in ctx.components()))
