@@ -231,6 +231,28 @@ asp_status asp_fit_active_set(asp_ctx *ctx, int64_t idx, const asp_gauss *init,
 asp_status asp_update_residual(asp_ctx *ctx, int64_t *pixels_touched);
 
 /*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the peak
+ * search of asp_find_peak (the largest |R|, the lowest row-major index on
+ * ties) over a caller's image, with no context and no allocation.
+ *   R          device image H x W, row-major FP32, 16-byte aligned; read only.
+ *   idx_out    device int64: the peak pixel r W + c.
+ *   value_out  device float: R at that pixel.
+ *   stream     the HIP stream (NULL: the null stream); the call is
+ *              asynchronous and may be captured into a graph.
+ * Its scratch (64 packed keys, 512 bytes) is a file-scope device array, one
+ * copy per GPU, held until the process ends; the call clears it with a
+ * kernel before every scan.  Calls that overlap on one GPU (other streams,
+ * other threads) share that array and race.  Returns ASP_ERR_INVALID_ARG for
+ * null pointers, H or W < 1, H W >= 2^32 - 1 (the maximum: the key holds a
+ * 32-bit index) or an unaligned image, with a message on stderr for the
+ * last two; ASP_ERR_DEVICE when a launch fails.  No hipMalloc, hipFree or
+ * allocating library call is made.
+ */
+asp_status asp_find_peak_noalloc(const float *R, int64_t H, int64_t W, int64_t *idx_out,
+                                 float *value_out, void *stream);
+
+/*
  * One evaluation of the fit objective on the device, the LM trial's own code
  * path (diagnostic; Sect. 3, Eq. 4 over the union U of the members' windows):
  * the m members' parameters theta (4 m doubles, (a, x, y, s), the new

@@ -23,7 +23,7 @@ MAX_SCALES = 8
 # Every symbol include/asp.h declares.
 EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destroy",
            "asp_last_error", "asp_find_peak", "asp_fit_active_set", "asp_update_residual",
-           "asp_last_fit", "asp_eval_trial",
+           "asp_last_fit", "asp_eval_trial", "asp_find_peak_noalloc",
            "asp_step", "asp_run", "asp_components", "asp_components_raw", "asp_residual",
            "asp_residual_device", "asp_psf_gauss", "asp_counts", "asp_fit_profile",
            "asp_kernel_timing", "asp_kernel_times", "asp_set_mlp", "asp_set_init_mode",
@@ -139,6 +139,7 @@ def lib():
         L.asp_fit_active_set.argtypes = [vp, i64, P(Gauss), P(FitReport)]
         L.asp_update_residual.argtypes = [vp, P(i64)]
         L.asp_last_fit.argtypes = [vp, P(FitReport)]
+        L.asp_find_peak_noalloc.argtypes = [vp, i64, i64, vp, vp, vp]
         L.asp_eval_trial.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, P(f64), P(f64), P(i64)]
         L.asp_step.argtypes = [vp]
         L.asp_run.argtypes = [vp, i64, P(RunReport)]
