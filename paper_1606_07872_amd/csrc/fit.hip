@@ -37,6 +37,7 @@ constexpr size_t kMatBytes = sizeof(double) * kMaxN * kMaxN;
 constexpr size_t kFitLds = kTileBytes + 2 * kMatBytes;   // tile (or A) | two Gram buffers
 constexpr int kGroup = 16;        // work-groups per first-level arrival group
 static_assert(kTileBytes >= kMatBytes, "A shares the tile buffer");
+static_assert(kTileBytes >= sizeof(float) * kUpdTabFloats, "the update's tables share the tile buffer");
 
 // Phase timer slots of DevState::prof.
 enum { kPCheckin = 0, kPSetup, kPEval, kPWait, kPReduce, kPLmStep, kPCommit, kPPrepare,
@@ -1330,7 +1331,7 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
                     // stores: acquire before reading it
                     if (t == 0) acquire_fence();
                     __syncthreads();
-                    update_tiles(p, wg, nwg);
+                    update_tiles(p, wg, nwg, tile);
                 }
                 return;
             }
@@ -1407,7 +1408,7 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
         }
     }
     publish(G);
-    if (!S.stop && S.upd) update_tiles(p, 0, nwg);
+    if (!S.stop && S.upd) update_tiles(p, 0, nwg, tile);
 }
 
 // ===========================================================================
@@ -1503,7 +1504,7 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
             if (cmd == kCmdPeak) {
                 peak_scan(P.R, P.H * P.W, (uint32_t)rank, (uint32_t)T, P.st->peak_keys);
             } else if (cmd == kCmdUpdate) {
-                update_tiles(P, rank, T);
+                update_tiles<1>(P, rank, T, tile);
             } else if (cmd == kCmdEval) {
                 prepare(P, S, ld_shared(&G->m), G->th_e, G->th_old, true);
                 const int64_t ntiles = (S.pref[S.m] + kT - 1) / kT;
@@ -1569,11 +1570,11 @@ __global__ __launch_bounds__(kT) void k_batch(BatchArgs b)
             }
             __syncthreads();
             if (T == 1 || S.upx <= b.solo_update_px) {
-                update_tiles(P, 0, 1);
+                update_tiles<1>(P, 0, 1, tile);
             } else {
                 if (t == 0) G->cmd = kCmdUpdate;
                 publish(G);
-                update_tiles(P, 0, T);
+                update_tiles<1>(P, 0, T, tile);
                 arrive(P, G, S, 0, T, 0);
                 if (!team_wait(G, S, ngroups, b.spin_ticks)) { ok = false; break; }
             }

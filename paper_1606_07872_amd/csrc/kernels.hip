@@ -50,8 +50,8 @@ hipError_t launch_peak_decode(const Params &p, hipStream_t s)
 
 __global__ __launch_bounds__(256) void k_update(Params p)
 {
-    if (!p.st->fit_ready) return;
-    update_tiles(p, blockIdx.x, gridDim.x);
+    __shared__ float tab[kUpdTabFloats];
+    update_tiles(p, blockIdx.x, gridDim.x, tab, true);
 }
 
 hipError_t launch_update(const Params &p, int grid, hipStream_t s)

@@ -409,7 +409,7 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     int64_t need = (n4 + 255) / 256;
     c->peak_grid = (int)(need < pg ? (need > 0 ? need : 1) : pg);
     // one slot of the tracked sum of R^2 per update work-group
-    c->update_grid = cus * 4 < asp::kSqSlots ? cus * 4 : asp::kSqSlots;
+    c->update_grid = cus * 8 < asp::kSqSlots ? cus * 8 : asp::kSqSlots;
 
     Params &P = c->P;
     P.R = c->R; P.H = H; P.W = W;

@@ -119,7 +119,9 @@ def test_lockstep_largest_active_set():
     peak = float(np.abs(dirty).max())
     ctx.run(40)                         # build up a crowd of components
     m_max, n_strict = 0, 0
-    for it in range(12):
+    for it in range(40):
+        if m_max >= 8 and n_strict >= 6:
+            break
         R0, comps0, k0 = ctx.residual(), ctx.components_raw(), ctx.counts()[0]
         rc, idx, val = ctx.find_peak()
         rc, rep = ctx.fit_active_set(idx)
