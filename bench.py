@@ -205,18 +205,25 @@ def full_run_leg(args, f, torch, asp):
                       max_active=f.max_active)
     del d_dirty, d_psf
     torch.cuda.synchronize()
+    prof0 = ctx.fit_profile()
     t0 = time.perf_counter()
     rc, rep = ctx.run(n)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     H, W = f.shape
     rms = tracked_rms(ctx, H * W)
+    prof1 = ctx.fit_profile()
+    hist = ctx.fit_histogram()
     out = {"iterations": rep["iterations"], "seconds": secs,
            "iterations_per_s": rep["iterations"] / secs if secs > 0 else 0.0,
            "components": rep["components"], "not_added": rep["not_added"],
            "trials_per_fit": rep["lm_trials"] / max(rep["iterations"], 1),
            "not_converged": rep["not_converged"], "rms": rms,
-           "rms_dirty": float(np.sqrt(np.mean(f.dirty.astype(np.float64) ** 2)))}
+           "rms_dirty": float(np.sqrt(np.mean(f.dirty.astype(np.float64) ** 2))),
+           "fit_phases_us": {k: round(prof1[k] - prof0[k], 1) for k in prof1},
+           "by_active_set": {int(m): {"fits": int(hist["fits"][m]), "trials": int(hist["trials"][m]),
+                                      "ms": round(float(hist["us"][m]) / 1e3, 2)}
+                             for m in range(len(hist["fits"])) if hist["fits"][m]}}
     log(f"full run {json.dumps(out)}")
     ab, wb = ctx.psf_gauss()
     o = oracle.Oracle(f.dirty, gain=f.gain, threshold=f.threshold, max_iter=n + args.full_samples,

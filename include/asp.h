@@ -368,11 +368,18 @@ asp_status asp_load_state(asp_ctx *ctx, const void *blob, int64_t bytes);
 asp_status asp_counts(asp_ctx *ctx, int64_t *k, int64_t *L);
 
 /* Diagnostics: accumulated fit-kernel phase timers of the work-group that
- * drives the fit, in microseconds, then event counts; n <= 12 entries:
+ * drives the fit, in microseconds, then event counts; n <= 14 entries:
  * check-in, setup, evaluation, waits, reduction, LM step, commit, trial
- * preparation, arrival, then trials, fits, pixels evaluated.  Reading does
- * not reset them. */
+ * preparation, arrival, then trials, fits, pixels evaluated, trials the
+ * driving work-group evaluated alone and their pixels.  Reading does not
+ * reset them. */
 asp_status asp_fit_profile(asp_ctx *ctx, double *out, int32_t n);
+
+/* Diagnostics: per active-set size m = 0 .. n - 1 (n <= ASP_MAX_ACTIVE + 1),
+ * the fits that ended with m members, their LM trials and their device time
+ * from the start values to the commit, in microseconds, summed since the
+ * context was created.  Each pointer is nullable. */
+asp_status asp_fit_histogram(asp_ctx *ctx, int64_t *fits, int64_t *trials, double *us, int32_t n);
 
 /*
  * Learned start values.  A perceptron 1024 -> 256 -> 256 -> 4 (ReLU) maps the

@@ -23,7 +23,7 @@ MAX_SCALES = 8
 # Every symbol include/asp.h declares.
 EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destroy",
            "asp_last_error", "asp_find_peak", "asp_fit_active_set", "asp_update_residual",
-           "asp_last_fit", "asp_eval_trial", "asp_find_peak_noalloc",
+           "asp_last_fit", "asp_eval_trial", "asp_find_peak_noalloc", "asp_fit_histogram",
            "asp_step", "asp_run", "asp_components", "asp_components_raw", "asp_residual",
            "asp_residual_device", "asp_psf_gauss", "asp_counts", "asp_fit_profile",
            "asp_kernel_timing", "asp_kernel_times", "asp_set_mlp", "asp_set_init_mode",
@@ -139,6 +139,7 @@ def lib():
         L.asp_fit_active_set.argtypes = [vp, i64, P(Gauss), P(FitReport)]
         L.asp_update_residual.argtypes = [vp, P(i64)]
         L.asp_last_fit.argtypes = [vp, P(FitReport)]
+        L.asp_fit_histogram.argtypes = [vp, vp, vp, vp, ctypes.c_int32]
         L.asp_find_peak_noalloc.argtypes = [vp, i64, i64, vp, vp, vp]
         L.asp_eval_trial.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, P(f64), P(f64), P(i64)]
         L.asp_step.argtypes = [vp]
@@ -362,12 +363,23 @@ class Context:
         return p.value
 
     PROFILE_FIELDS = ("checkin_us", "setup_us", "eval_us", "wait_us", "reduce_us", "lmstep_us",
-                      "commit_us", "prepare_us", "arrive_us", "trials", "fits", "eval_px")
+                      "commit_us", "prepare_us", "arrive_us", "trials", "fits", "eval_px",
+                      "solo_trials", "solo_px")
 
     def fit_profile(self) -> dict:
         out = np.zeros(len(self.PROFILE_FIELDS))
         self._check(lib().asp_fit_profile(self._ctx, out.ctypes.data, len(out)))
         return dict(zip(self.PROFILE_FIELDS, out.tolist()))
+
+    def fit_histogram(self) -> dict:
+        """Per active-set size m: fits, LM trials and device microseconds."""
+        n = MAX_ACTIVE + 1
+        fits = np.zeros(n, dtype=np.int64)
+        trials = np.zeros(n, dtype=np.int64)
+        us = np.zeros(n)
+        self._check(lib().asp_fit_histogram(self._ctx, fits.ctypes.data, trials.ctypes.data,
+                                            us.ctypes.data, n))
+        return {"fits": fits, "trials": trials, "us": us}
 
     KERNEL_KINDS = ("peak", "fit", "update", "propose", "smooth_passes", "smooth_pick",
                     "refresh", "eval2004", "update2004")

@@ -24,7 +24,7 @@ struct Rect {
     int32_t pad;
 };
 
-constexpr int kProfSlots = 12;
+constexpr int kProfSlots = 14;
 
 constexpr int kPeakSlots = 64;   // wave-size: one slot per lane of the collecting wave
 
@@ -83,6 +83,9 @@ struct DevState {
     int32_t psf_status, pad1;
     // fit phase timers (device wall clock ticks) and event counts
     unsigned long long prof[kProfSlots];
+    // per active-set size m: fits, their LM trials and their wall-clock ticks
+    // (start values to commit)
+    unsigned long long fits_m[kMaxM + 1], trials_m[kMaxM + 1], ticks_m[kMaxM + 1];
     // training-sample recording: slots filled
     int64_t rec_n;
     // the smoothing method: this iteration smooths; smooth_start is current

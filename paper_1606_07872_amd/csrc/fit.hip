@@ -41,10 +41,14 @@ static_assert(kTileBytes >= sizeof(float) * kUpdTabFloats, "the update's tables 
 
 // Phase timer slots of DevState::prof.
 enum { kPCheckin = 0, kPSetup, kPEval, kPWait, kPReduce, kPLmStep, kPCommit, kPPrepare,
-       kPArrive, kPTrials, kPFits, kPEvalPx };
-static_assert(kPEvalPx + 1 == kProfSlots, "profile slots");
+       kPArrive, kPTrials, kPFits, kPEvalPx, kPSoloTrials, kPSoloPx };
+static_assert(kPSoloPx + 1 == kProfSlots, "profile slots");
 
 __device__ inline unsigned long long now_ticks() { return wall_clock64(); }
+
+// Polling loops sleep this many units of 64 clocks between reads of a
+// counter another work-group advances (fewer reads of one line while waiting).
+constexpr int kPollSleep = 8;
 
 struct WGShared {
     // member constants at the parameters under evaluation
@@ -81,6 +85,7 @@ struct WGShared {
     int64_t k_target, upx;
     // control
     unsigned long long tmark;      // phase timer mark (thread 0)
+    unsigned long long tfit;       // start of the fit (thread 0)
     unsigned int gen;
     int32_t last, abort, done, ok, finished, accept, stop;
     int32_t upd;                   // the fit committed and this launch also updates R
@@ -144,7 +149,7 @@ __device__ __forceinline__ bool wait_publish(FitGlobal *G, WGShared &S, unsigned
                 if (b != last_beat) { last_beat = b; t0 = tn; }
             }
             if (tn - t0 > limit) break;
-            __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_s_sleep(kPollSleep);
         }
         S.abort = (now == S.gen) ? 1 : 0;
         S.gen = now;
@@ -171,7 +176,7 @@ __device__ __forceinline__ bool spin_until(unsigned int *ctr, unsigned int targe
     bool ok = true;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (now_ticks() - t0 > limit) { ok = false; break; }
-        __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_s_sleep(kPollSleep);
     }
     if (acquire) acquire_fence();
     return ok;
@@ -1204,10 +1209,12 @@ __device__ __forceinline__ bool trial_eval(const Params &p, FitGlobal *G, WGShar
     double *He = H2 + (1 - S.hsel) * (kMaxN * kMaxN);   // the trial's buffer
     if (ntiles <= p.solo_tiles) {
         // small: the leading work-group alone, no publication
+        if (t == 0) atomicAdd(&p.st->prof[kPSoloTrials], 1ull);
         evaluate_row(p, S, tile, red, 0, 1, p.partials);
         lap(p, S, kPEval);
         reduce_partials(p, S, 0, 1, He);
         lap(p, S, kPReduce);
+        if (t == 0) atomicAdd(&p.st->prof[kPSoloPx], (unsigned long long)S.npx_e);
         return true;
     }
     // large: every work-group takes a share
@@ -1250,6 +1257,7 @@ __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShar
     DevState *st = p.st;
     const int t = threadIdx.x;
     mark(S);
+    if (t == 0) S.tfit = S.tmark;
     setup_fit(p, G, S, S.use_prop != 0);
     lap(p, S, kPSetup);
     for (;;) {
@@ -1279,6 +1287,12 @@ __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShar
         mark(S);
         commit(p, S);
         lap(p, S, kPCommit);
+        if (t == 0) {
+            const int m = S.m;
+            st->fits_m[m] += 1ull;
+            st->trials_m[m] += (unsigned long long)(S.trials_total + S.trials);
+            st->ticks_m[m] += now_ticks() - S.tfit;
+        }
         return true;
     }
 }

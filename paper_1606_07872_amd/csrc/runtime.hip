@@ -926,6 +926,8 @@ asp_status asp_eval_trial(asp_ctx *c, int32_t m, const double *theta, const doub
 {
     if (!c || m < 1 || m > ASP_MAX_ACTIVE || !theta || (m > 1 && !stored))
         return ASP_ERR_INVALID_ARG;
+    if (m > c->opt.max_active)
+        return fail(c, ASP_ERR_INVALID_ARG, "more members than the context's max_active");
     if (c->phase != 0) return fail(c, ASP_ERR_STATE, "asp_eval_trial inside a step-API sequence");
     for (int i = 0; i < 4 * m; ++i)
         if (!isfinite(theta[i]) || (i >= 4 && !isfinite(stored[i])))
@@ -1180,6 +1182,23 @@ asp_status asp_fit_profile(asp_ctx *c, double *out, int32_t n)
     for (int i = 0; i < n; ++i) {
         const double v = (double)c->st_host->prof[i];
         out[i] = (i < 9) ? v * us_per_tick : v;   // 9 timers, then counts
+    }
+    return ASP_OK;
+}
+
+asp_status asp_fit_histogram(asp_ctx *c, int64_t *fits, int64_t *trials, double *us, int32_t n)
+{
+    if (!c || n < 0 || n > ASP_MAX_ACTIVE + 1) return ASP_ERR_INVALID_ARG;
+    asp_status s = pull_all(c);
+    if (s != ASP_OK) return s;
+    int rate_khz = 100000;
+    (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device);
+    const double us_per_tick = 1000.0 / (double)(rate_khz > 0 ? rate_khz : 100000);
+    const DevState *h = c->st_host;
+    for (int m = 0; m < n; ++m) {
+        if (fits) fits[m] = (int64_t)h->fits_m[m];
+        if (trials) trials[m] = (int64_t)h->trials_m[m];
+        if (us) us[m] = (double)h->ticks_m[m] * us_per_tick;
     }
     return ASP_OK;
 }
