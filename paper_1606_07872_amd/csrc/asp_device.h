@@ -189,14 +189,21 @@ struct Params {
     SmoothParams sm;
 };
 
-// The proposal network in the layout of the inference kernel: W1 and W2
-// transposed (input-major) so that the threads of a work-group, one per
-// output unit, read consecutive addresses.
+// The proposal network in the layout of the inference kernel: W1 row-major
+// (as trained), W2 transposed (input-major), then W3 and the biases.  The
+// kernel runs kPropGroups work-groups, each owning kNetH / kPropGroups units
+// of the first hidden layer; their partial sums of the second layer and an
+// arrival counter sit in a scratch area of kNetScratch floats after the
+// weights.
 constexpr int kNetIn = 1024, kNetH = 256, kNetOut = 4, kPatch = 32, kPatchHalf = 16;
 constexpr int64_t kNetParams = (int64_t)kNetH * kNetIn + kNetH + (int64_t)kNetH * kNetH + kNetH +
                                (int64_t)kNetOut * kNetH + kNetOut;
+constexpr int kPropGroups = 64;
+constexpr int64_t kNetScratch = (int64_t)kPropGroups * kNetH + 64;
 struct NetParams {
-    const float *w1t, *b1, *w2t, *b2, *w3, *b3;
+    const float *w1, *b1, *w2t, *b2, *w3, *b3;
+    float *part;                   // kPropGroups x kNetH second-layer partial sums
+    unsigned int *done;            // arrivals, counted modulo kPropGroups
 };
 
 // ---------------------------------------------------------------------------

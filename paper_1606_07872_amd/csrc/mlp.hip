@@ -14,8 +14,8 @@
 // W3 (4 x 256), b3; 329220 FP32 values.
 //
 // This file holds
-//   * the inference kernel of the minor cycle (one work-group per iteration,
-//     which also records (patch, target) training pairs when asked),
+//   * the inference kernel of the minor cycle (64 work-groups, which also
+//     record the patch of (patch, target) training pairs when asked),
 //   * the training kernels: a tiled FP32 GEMM with fused bias / ReLU / ReLU
 //     mask epilogues, column sums, the MSE gradient, Adam and a row gather,
 //   * the trainer object of the C ABI (asp_mlp_*).
@@ -33,60 +33,158 @@ namespace asp {
 // Inference inside the minor cycle.
 // ===========================================================================
 
-constexpr int kPT = 256;   // threads of the proposal kernel
+constexpr int kPT = 256;                          // threads per work-group
+constexpr int kUnits = kNetH / kPropGroups;       // first-layer units per work-group
+constexpr int kPerThread = kNetIn / kPT;          // patch inputs per thread
+static_assert(kNetH == kPT, "one thread per second-layer unit");
+static_assert(kNetOut * 64 == kPT, "one wave per output");
+static_assert(kUnits * kPropGroups == kNetH && kUnits == 4, "four first-layer units per group");
+static_assert(kPerThread == 4 && kPatch % kPerThread == 0, "four inputs of one patch row");
 
+// The peak pixel of this iteration (the forced index of a caller's fit, else
+// the decoded peak key) and the residual there; false when there is none (the
+// fit kernel reports that state) or after a stop.  The stop flag, the forced
+// index and the key slots are read in one round trip.  Every thread of the
+// work-group calls it.
+__device__ inline bool proposal_centre(const Params &p, unsigned long long *key_s, int64_t *r0,
+                                       int64_t *c0, float *v)
+{
+    DevState *st = p.st;
+    const int32_t stop = st->stop;
+    int64_t idx = st->forced_idx;
+    const unsigned long long key = collect_peak_key(st, false, key_s);
+    if (stop) return false;
+    if (idx < 0) {
+        if (key == 0ull) return false;
+        idx = (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+    }
+    if (idx >= p.H * p.W) return false;
+    *r0 = idx / p.W;
+    *c0 = idx % p.W;
+    *v = p.R[idx];
+    return true;
+}
+
+// One launch of kPropGroups work-groups.  Work-group g:
+//   * gathers the whole patch (thread t holds inputs 4t .. 4t+3, four
+//     neighbours of one patch row) and, when the context collects training
+//     pairs, records inputs 16g .. 16g+15;
+//   * forms first-layer units 4g .. 4g+3 completely (per-thread products,
+//     then a fixed-order reduction over lanes and waves);
+//   * writes the contribution of those four units to every second-layer
+//     pre-activation (thread u: unit u), one row of the partial-sum scratch.
+// The work-group that arrives last adds the rows in work-group order, applies
+// the bias and ReLU, runs the output layer and writes the proposal.  Every
+// load that does not depend on another is issued at the start.  Without a
+// peak, or after a stop, every work-group leaves before the arrival, so the
+// counter stays a multiple of the grid.
 __global__ __launch_bounds__(kPT) void k_propose(Params p, NetParams net, int use_net)
 {
     DevState *st = p.st;
-    if (st->stop) return;
-    __shared__ float xs[kNetIn];
-    __shared__ float h1[kNetH], h2[kNetH];
+    __shared__ float red[kPT / 64][kUnits];
+    __shared__ float h1[kUnits];
+    __shared__ float h2[kNetH];
     __shared__ float outs[kNetOut];
     __shared__ unsigned long long key_s;
-    const int t = threadIdx.x;
-    int64_t idx = st->forced_idx;
-    const unsigned long long key = collect_peak_key(st, false, &key_s);
-    if (idx < 0) {
-        if (key == 0ull) return;     // the fit kernel reports the bad state
-        idx = (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+    __shared__ int last_s;
+    const int t = threadIdx.x, g = blockIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    float4 w1[kUnits];
+    float w2[kUnits], w3[kNetH / 64];
+    float b1 = 0.0f, b2 = 0.0f, b3 = 0.0f;
+    if (use_net) {
+#pragma unroll
+        for (int j = 0; j < kUnits; ++j)
+            w1[j] = *reinterpret_cast<const float4 *>(net.w1 + (int64_t)(g * kUnits + j) * kNetIn +
+                                                      kPerThread * t);
+#pragma unroll
+        for (int j = 0; j < kUnits; ++j) w2[j] = net.w2t[(g * kUnits + j) * kNetH + t];
+#pragma unroll
+        for (int i = 0; i < kNetH / 64; ++i) w3[i] = net.w3[wave * kNetH + lane + 64 * i];
+        b1 = t < kUnits ? net.b1[g * kUnits + t] : 0.0f;
+        b2 = net.b2[t];
+        b3 = lane == 0 ? net.b3[wave] : 0.0f;
     }
-    if (idx >= p.H * p.W) return;
-    const int64_t r0 = idx / p.W, c0 = idx % p.W;
-    const float v = p.R[idx];
-    const bool rec = p.rec_cap > 0 && st->rec_n < p.rec_cap;
-    float *rp = rec ? p.rec_patch + st->rec_n * kNetIn : nullptr;
-    for (int e = t; e < kNetIn; e += kPT) {
-        const int64_t r = r0 - kPatchHalf + e / kPatch, c = c0 - kPatchHalf + e % kPatch;
-        const float val = (r >= 0 && r < p.H && c >= 0 && c < p.W) ? p.R[r * p.W + c] / v : 0.0f;
-        xs[e] = val;
-        if (rec) rp[e] = val;
+    int64_t r0, c0;
+    float v;
+    if (!proposal_centre(p, &key_s, &r0, &c0, &v)) return;
+    float x[kPerThread];
+    {
+        const int e0 = kPerThread * t;
+        const int64_t r = r0 - kPatchHalf + e0 / kPatch;
+        const int64_t cb = c0 - kPatchHalf + e0 % kPatch;
+        const bool row_in = r >= 0 && r < p.H;
+#pragma unroll
+        for (int i = 0; i < kPerThread; ++i) {
+            const int64_t c = cb + i;
+            x[i] = (row_in && c >= 0 && c < p.W) ? p.R[r * p.W + c] / v : 0.0f;
+        }
+        if (p.rec_cap > 0 && (e0 >> 4) == g && st->rec_n < p.rec_cap) {
+            float *rp = p.rec_patch + st->rec_n * kNetIn + e0;
+#pragma unroll
+            for (int i = 0; i < kPerThread; ++i) rp[i] = x[i];
+        }
     }
     if (!use_net) return;
-    __syncthreads();
-    // layer 1: thread t is output unit t; W1 is stored input-major
+    // first layer: units 4g .. 4g+3
     {
-        float acc = net.b1[t];
-        const float *w = net.w1t + t;
-#pragma unroll 8
-        for (int k = 0; k < kNetIn; ++k) acc += w[(int64_t)k * kNetH] * xs[k];
-        h1[t] = acc > 0.0f ? acc : 0.0f;
+        float acc[kUnits];
+#pragma unroll
+        for (int j = 0; j < kUnits; ++j)
+            acc[j] = w1[j].x * x[0] + w1[j].y * x[1] + w1[j].z * x[2] + w1[j].w * x[3];
+#pragma unroll
+        for (int j = 0; j < kUnits; ++j)
+            for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, 64);
+        if (lane < kUnits) {
+            float a = acc[0];
+#pragma unroll
+            for (int j = 1; j < kUnits; ++j) a = lane == j ? acc[j] : a;
+            red[wave][lane] = a;
+        }
+        __syncthreads();
+        if (t < kUnits) {
+            float a = b1;
+#pragma unroll
+            for (int q = 0; q < kPT / 64; ++q) a += red[q][t];
+            h1[t] = a > 0.0f ? a : 0.0f;
+        }
+        __syncthreads();
+    }
+    // this group's share of every second-layer pre-activation
+    {
+        float a = 0.0f;
+#pragma unroll
+        for (int j = 0; j < kUnits; ++j) a += w2[j] * h1[j];
+        net.part[g * kNetH + t] = a;
+    }
+    // arrival: the barrier orders every thread's stores before thread 0's
+    // release; the last arrival's acquire pairs with the others' releases
+    __syncthreads();
+    if (t == 0) {
+        const unsigned int before = __hip_atomic_fetch_add(net.done, 1u, __ATOMIC_ACQ_REL,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+        last_s = (before + 1u) % kPropGroups == 0u ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last_s) return;
+    {
+        float part[kPropGroups];
+#pragma unroll
+        for (int q = 0; q < kPropGroups; ++q)
+            part[q] = __hip_atomic_load(&net.part[q * kNetH + t], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+        float a = b2;
+#pragma unroll
+        for (int q = 0; q < kPropGroups; ++q) a += part[q];
+        h2[t] = a > 0.0f ? a : 0.0f;
     }
     __syncthreads();
     {
-        float acc = net.b2[t];
-        const float *w = net.w2t + t;
-#pragma unroll 8
-        for (int k = 0; k < kNetH; ++k) acc += w[k * kNetH] * h1[k];
-        h2[t] = acc > 0.0f ? acc : 0.0f;
-    }
-    __syncthreads();
-    // layer 3: wave j computes output j
-    {
-        const int wave = t >> 6, lane = t & 63;
-        float acc = 0.0f;
-        for (int k = lane; k < kNetH; k += 64) acc += net.w3[wave * kNetH + k] * h2[k];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0) outs[wave] = acc + net.b3[wave];
+        float a = 0.0f;
+#pragma unroll
+        for (int i = 0; i < kNetH / 64; ++i) a += w3[i] * h2[lane + 64 * i];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        if (lane == 0) outs[wave] = a + b3;
     }
     __syncthreads();
     if (t == 0) {
@@ -99,12 +197,9 @@ __global__ __launch_bounds__(kPT) void k_propose(Params p, NetParams net, int us
     }
 }
 
-static_assert(kNetOut * 64 == kPT, "one wave per output");
-static_assert(kNetH == kPT, "one thread per hidden unit");
-
 hipError_t launch_propose(const Params &p, const NetParams &net, int use_net, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_propose, dim3(1), dim3(kPT), 0, s, p, net, use_net);
+    hipLaunchKernelGGL(k_propose, dim3(kPropGroups), dim3(kPT), 0, s, p, net, use_net);
     return hipGetLastError();
 }
 
@@ -276,11 +371,9 @@ __global__ void k_transpose(const float *w, int rows, int cols, float *wt)
 hipError_t launch_net_layout(const float *flat, float *net, hipStream_t s)
 {
     // flat: W1 (256 x 1024), b1, W2 (256 x 256), b2, W3, b3
-    // net:  W1^T (1024 x 256), b1, W2^T (256 x 256), b2, W3, b3
+    // net:  W1, b1, W2^T (256 x 256), b2, W3, b3
     const int64_t n1 = (int64_t)kNetH * kNetIn, n2 = (int64_t)kNetH * kNetH;
-    hipLaunchKernelGGL(k_transpose, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, flat,
-                       kNetH, kNetIn, net);
-    hipError_t e = hipMemcpyAsync(net + n1, flat + n1, sizeof(float) * kNetH,
+    hipError_t e = hipMemcpyAsync(net, flat, sizeof(float) * (n1 + kNetH),
                                   hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_transpose, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s,

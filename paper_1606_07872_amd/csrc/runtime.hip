@@ -1230,18 +1230,26 @@ asp_status asp_set_mlp(asp_ctx *c, const float *weights, int64_t n)
     HIP_OR_FAIL(c, hipMalloc(&flat, sizeof(float) * asp::kNetParams));
     hipError_t e = hipMemcpyAsync(flat, weights, sizeof(float) * asp::kNetParams,
                                   hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess && !c->net) e = hipMalloc(&c->net, sizeof(float) * asp::kNetParams);
+    if (e == hipSuccess && !c->net)
+        e = hipMalloc(&c->net, sizeof(float) * (asp::kNetParams + asp::kNetScratch));
     if (e == hipSuccess) e = asp::launch_net_layout(flat, c->net, c->stream);
+    // the proposal kernel's arrival counter starts at a multiple of its grid
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->net + asp::kNetParams + (int64_t)asp::kPropGroups * asp::kNetH, 0,
+                           sizeof(unsigned int), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(flat);
     if (e != hipSuccess) return fail(c, ASP_ERR_DEVICE, std::string("asp_set_mlp: ") + hipGetErrorString(e));
     const int64_t n1 = (int64_t)asp::kNetH * asp::kNetIn, n2 = (int64_t)asp::kNetH * asp::kNetH;
-    c->netp.w1t = c->net;
+    c->netp.w1 = c->net;
     c->netp.b1 = c->net + n1;
     c->netp.w2t = c->net + n1 + asp::kNetH;
     c->netp.b2 = c->net + n1 + asp::kNetH + n2;
     c->netp.w3 = c->net + n1 + 2 * asp::kNetH + n2;
     c->netp.b3 = c->netp.w3 + (int64_t)asp::kNetOut * asp::kNetH;
+    c->netp.part = c->net + asp::kNetParams;
+    c->netp.done = reinterpret_cast<unsigned int *>(c->netp.part +
+                                                    (int64_t)asp::kPropGroups * asp::kNetH);
     return ASP_OK;
 }
 
