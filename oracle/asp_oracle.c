@@ -693,8 +693,13 @@ static int step_impl(orc_state *st, const double *init, const double *start4, or
         rc = fit_from(st, plain, plain, p4, &won, rep, theta, &lmr, hess_out);
         if (rc != ORC_OK) return rep->status = rc;
         rep->start_from_proposal = won;
-        if (won && !lmr.converged) {
-            /* The simple initial values are the fallback. */
+        if (won && (!lmr.converged || theta[0] == 0.0)) {
+            /* The simple initial values are the fallback of a proposal that
+             * failed: LM did not converge from it, or converged to a new
+             * component of zero amplitude (a start that explains none of the
+             * peak's emission; without the fallback such a fit can leave the
+             * model unchanged and bring the same peak and the same proposal
+             * back every iteration). */
             used_fallback = 1;
             int tr = lmr.trials;
             rc = fit_from(st, plain, plain, NULL, NULL, rep, theta, &lmr, hess_out);

@@ -1272,9 +1272,11 @@ __device__ __forceinline__ bool fit_trials(const Params &p, FitGlobal *G, WGShar
             atomicAdd(&st->prof[kPEvalPx], npx);
         }
         if (!S.finished) continue;
-        if (S.use_prop && S.chose_prop && !S.converged && S.pass == 0) {
-            // LM started from the proposal and did not converge: the simple
-            // values instead
+        if (S.use_prop && S.chose_prop && S.pass == 0 && (!S.converged || S.th_c[0] == 0.0)) {
+            // LM started from the proposal and did not converge, or converged
+            // to a new component of zero amplitude (which can leave the model
+            // unchanged, so that the same peak and proposal come back): the
+            // simple values instead
             if (t == 0) {
                 S.trials_total += S.trials;
                 S.used_fallback = 1;

@@ -96,3 +96,4 @@ def test_encode_decode_round_trip():
     t = mlp.encode(theta, 57 * 200 + 100, 200, 0.5, 1.3)
     np.testing.assert_allclose(t, [0.74, np.log(4.2 / 1.3), 1.25, 0.5], rtol=1e-15)
     np.testing.assert_allclose(mlp.decode(t, 57 * 200 + 100, 200, 0.5, 1.3), theta, rtol=1e-15)
+

@@ -253,6 +253,37 @@ def test_zero_amplitude_new_component_is_not_added(orc):
     assert np.abs(o.R - expect).max() <= 1e-12
 
 
+def test_zero_amplitude_fit_from_a_proposal_falls_back(orc):
+    """The state of the test above with a proposal near the peak (narrower
+    than the old member) that beats the simple values at the start: LM from it
+    converges to a new component of amplitude zero, a failed proposal, so the
+    simple values are fitted instead.  The iteration then ends as the plain one
+    does (same residual, same list), and its trial count holds both fits."""
+    H = W = 64
+    wb = 1.2
+    A = [1.0, 30.0, 30.0, 4.0]
+    A0 = [0.5, 32.0, 30.0, 4.0]
+    dip = [0.005, 29.0, 30.0, wb]
+    R = truncated(H, W, A) - truncated(H, W, A0) - truncated(H, W, dip)
+    prop = [R[30, 29], 29.2, 30.0, 1.5]
+
+    def fresh():
+        o = orc.Oracle(R, gain=1.0, max_iter=10, max_active=5, alpha_b=1.0, omega_b=wb)
+        o.load_state(R, np.array([A0]), 1)
+        return o
+
+    plain = fresh()
+    rp = plain.step()
+    o = fresh()
+    rep = o.step(init=prop)
+    assert rep["start_from_proposal"] and rep["used_fallback"] and rep["converged"]
+    assert rep["theta"][0][0] == 0.0 and not rep["added"]
+    assert rep["lm_iters"] > rp["lm_iters"]
+    assert o.L == plain.L == 1
+    np.testing.assert_array_equal(o.R, plain.R)
+    np.testing.assert_array_equal(o.comps(), plain.comps())
+
+
 def test_field_run_adds_no_zero_amplitude_component(orc):
     """On the 1024^2 EVLA-like field (seed 1000) the joint fits often leave the
     new component at zero amplitude, an old member explaining the peak; none
