@@ -99,13 +99,16 @@ __device__ inline void peak_scan(const float *__restrict__ R, int64_t n, uint32_
 // circular Gaussian is separable, G(r, c) = a e^{-dy^2/2s^2} e^{-dx^2/2s^2}:
 // per tile and rect the work-group tabulates the row factors (with the
 // amplitude) and the 256 column factors in LDS, both zero outside the rect,
-// so a pixel costs one FMA per rect and no exponential.  A thread takes four
-// consecutive columns of kUpdPer rows (rows lr, lr + 4, ...): its float4 loads
-// issued together, and float4 stores, when W is a multiple of 4.
+// so a pixel costs one FMA per rect and no exponential.  The tables hold
+// kUpdChunk rects at a time (more rects take several passes over the same
+// tile, adding in rect order), which keeps a work-group's LDS near 11 KiB:
+// eight work-groups fit on a CU.  A thread takes four consecutive columns of
+// kUpdPer rows (rows lr, lr + 4, ...): its float4 loads issued together, and
+// float4 stores, when W is a multiple of 4.
 // ===========================================================================
 
-constexpr int kUpdCols = 256, kUpdRowStep = 4, kUpdRowsMax = 16;
-constexpr int kUpdTabFloats = kMaxRects * (kUpdCols + kUpdRowsMax);   // factor tables in LDS
+constexpr int kUpdCols = 256, kUpdRowStep = 4, kUpdRowsMax = 16, kUpdChunk = 8;
+constexpr int kUpdTabFloats = kUpdChunk * (kUpdCols + kUpdRowsMax);   // factor tables in LDS
 
 template <int kUpdPer = 4>
 __device__ inline void update_tiles(const Params &p, int rank, int size, float *tab,
@@ -124,8 +127,8 @@ __device__ inline void update_tiles(const Params &p, int rank, int size, float *
     __shared__ double *sq_slot;
     __shared__ unsigned long long *px_slot;
     __shared__ PeakTiles pk_s;
-    float *fx = tab;                               // [rect][column of the tile]
-    float *fy = tab + kMaxRects * kUpdCols;        // [rect][row of the tile], amplitude folded in
+    float *fx = tab;                               // [rect of the chunk][column of the tile]
+    float *fy = tab + kUpdChunk * kUpdCols;        // [rect of the chunk][row], amplitude folded in
     const int t = threadIdx.x;
     __syncthreads();
     // the plan, read in one round trip: every rect slot is read, the unused
@@ -195,21 +198,6 @@ __device__ inline void update_tiles(const Params &p, int rank, int size, float *
                 }
             }
         }
-        // the factor tables of this tile (the loads above are in flight)
-        for (int e = t; e < nr * (kUpdCols + kUpdRows); e += blockDim.x) {
-            const int i = e / (kUpdCols + kUpdRows), j = e - i * (kUpdCols + kUpdRows);
-            if (j < kUpdCols) {
-                const int32_t cc = tc0 + j;
-                const bool in = cc >= rb[i][2] && cc <= rb[i][3];
-                const float dx = (float)(cc - rcx[i]) - rfx[i];
-                fx[i * kUpdCols + j] = in ? __expf(-(dx * dx) * rinv[i]) : 0.0f;
-            } else {
-                const int32_t rr = tr0 + (j - kUpdCols);
-                const bool in = rr >= rb[i][0] && rr <= rb[i][1];
-                const float dy = (float)(rr - rcy[i]) - rfy[i];
-                fy[i * kUpdRows + (j - kUpdCols)] = in ? ramp[i] * __expf(-(dy * dy) * rinv[i]) : 0.0f;
-            }
-        }
         for (int e = t; e < kUpdCols + kUpdRows; e += blockDim.x) {
             uint32_t bits = 0u;
             if (e < kUpdCols) {
@@ -224,7 +212,43 @@ __device__ inline void update_tiles(const Params &p, int rank, int size, float *
                 rowbits[e - kUpdCols] = bits;
             }
         }
-        __syncthreads();
+        float acc[kUpdPer][4];
+#pragma unroll
+        for (int k = 0; k < kUpdPer; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[k][j] = 0.0f;
+        for (int i0 = 0; i0 < nr; i0 += kUpdChunk) {
+            const int nc = nr - i0 < kUpdChunk ? nr - i0 : kUpdChunk;
+            if (i0 > 0) __syncthreads();           // the last chunk's tables are read
+            // the factor tables of this chunk (the first while the loads above
+            // are in flight)
+            for (int e = t; e < nc * (kUpdCols + kUpdRows); e += blockDim.x) {
+                const int ic = e / (kUpdCols + kUpdRows), j = e - ic * (kUpdCols + kUpdRows);
+                const int i = i0 + ic;
+                if (j < kUpdCols) {
+                    const int32_t cc = tc0 + j;
+                    const bool in = cc >= rb[i][2] && cc <= rb[i][3];
+                    const float dx = (float)(cc - rcx[i]) - rfx[i];
+                    fx[ic * kUpdCols + j] = in ? __expf(-(dx * dx) * rinv[i]) : 0.0f;
+                } else {
+                    const int32_t rr = tr0 + (j - kUpdCols);
+                    const bool in = rr >= rb[i][0] && rr <= rb[i][1];
+                    const float dy = (float)(rr - rcy[i]) - rfy[i];
+                    fy[ic * kUpdRows + (j - kUpdCols)] =
+                        in ? ramp[i] * __expf(-(dy * dy) * rinv[i]) : 0.0f;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kUpdPer; ++k) {
+                for (int ic = 0; ic < nc; ++ic) {
+                    const float gy = fy[ic * kUpdRows + lr + kUpdRowStep * k];
+                    const float *gx = fx + ic * kUpdCols + lq;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[k][j] += gy * gx[j];
+                }
+            }
+        }
         uint32_t cb[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) cb[j] = colbits[lq + j];
@@ -235,19 +259,12 @@ __device__ inline void update_tiles(const Params &p, int rank, int size, float *
             const int64_t q = (int64_t)r * p.W + c;
             const uint32_t rbits = rowbits[lr + kUpdRowStep * k];
             bool hit[4];
-            float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int j = 0; j < 4; ++j) hit[j] = (rbits & cb[j]) != 0u;
-            for (int i = 0; i < nr; ++i) {
-                const float gy = fy[i * kUpdRows + lr + kUpdRowStep * k];
-                const float *gx = fx + i * kUpdCols + lq;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[j] += gy * gx[j];
-            }
             float nv[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                nv[j] = hit[j] ? v[k][j] + acc[j] : v[k][j];
+                nv[j] = hit[j] ? v[k][j] + acc[k][j] : v[k][j];
                 if (hit[j]) {
                     dsq += (double)nv[j] * nv[j] - (double)v[k][j] * v[k][j];
                     ++cnt32;

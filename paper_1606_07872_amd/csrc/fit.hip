@@ -1028,7 +1028,8 @@ __device__ __forceinline__ void commit(const Params &p, WGShared &S)
         st->not_converged += S.converged ? 0ull : 1ull;
         st->fallbacks += (unsigned long long)S.used_fallback;
         st->init_source = S.use_prop ? st->have_proposal : (S.use_smooth ? 3 : 0);
-        st->start_prop = S.chose_prop && !S.used_fallback;
+        // a fallback follows only a fit that started from the proposal
+        st->start_prop = (S.chose_prop || S.used_fallback) ? 1 : 0;
         for (int i = 0; i < 4; ++i)
             st->init[i] = S.use_prop ? st->proposal[i] : (S.use_smooth ? S.t0[i] : 0.0);
         st->have_proposal = 0;

@@ -55,18 +55,27 @@ class Lockstep:
         self.peak = float(np.abs(field.dirty).max())
         self.records = []
 
-    def step(self, init=None):
+    def step(self, init=None, learned=False):
+        """One lockstep iteration.  With `learned` the context is in learned
+        mode: the device fits from its network's proposal first, and the
+        oracle then fits from that same proposal."""
         ctx, orc = self.ctx, self.orc
         R0 = ctx.residual()
         comps0 = ctx.components_raw()
         k0, _ = ctx.counts()
         rc, idx, val = ctx.find_peak()
         orc.load_state(R0, comps0, k0)
-        orep = orc.step(init=init, want_hess=True)
         if rc != 0:
+            orep = orc.step(init=init, want_hess=True)
             assert orep["status"] == rc, (rc, orep["status"])
             return None
-        rc, rep = ctx.fit_active_set(idx, init=init)
+        if learned:
+            rc, rep = ctx.fit_active_set(idx)
+            assert rep["init_source"] == 2, rep["init_source"]
+            orep = orc.step(init=rep["init"], want_hess=True)
+        else:
+            orep = orc.step(init=init, want_hess=True)
+            rc, rep = ctx.fit_active_set(idx, init=init)
         ctx.update_residual()
         R1 = ctx.residual().astype(np.float64)
         rec = {"k": k0, "idx": idx, "orc_idx": orep["idx"], "members": rep["members"],
@@ -75,6 +84,8 @@ class Lockstep:
                "orc_theta": orep["theta"], "resid_err": float(np.abs(R1 - orc.R).max()),
                "gpu_trials": rep["lm_iters"], "orc_trials": orep["lm_iters"],
                "added": rep["added"], "orc_added": orep["added"],
+               "prop": rep["start_from_proposal"], "orc_prop": orep["start_from_proposal"],
+               "fallback": rep["used_fallback"], "orc_fallback": orep["used_fallback"],
                "cond": scaled_cond(orep["hess"]) if "hess" in orep else 0.0}
         if rec["members"] == rec["orc_members"]:
             rec["param_err"] = param_errors(rep["theta"], orep["theta"])
@@ -97,6 +108,7 @@ class Lockstep:
         assert rec["members"] == rec["orc_members"], rec
         assert rec["resid_err"] <= RESID_TOL * self.peak, (rec["resid_err"], rec["k"])
         assert rec["added"] == rec["orc_added"], rec
+        assert rec["prop"] == rec["orc_prop"], rec
         assert rec["n_comps"] == rec["orc_n_comps"], rec
         assert rec["untouched_equal"], rec
         if strict and rec["cond"] <= COND_MAX:
