@@ -420,6 +420,17 @@ __device__ __forceinline__ void prepare(const Params &p, WGShared &S, int m, con
     __syncthreads();
 }
 
+// Orders the LDS accesses of one wave: the lanes of a wave issue LDS
+// instructions together and the LDS serves them in program order, so after
+// this point every lane sees what any lane of the wave wrote before it; the
+// wavefront-scope fences keep the compiler from moving accesses across.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline double wave_sum(double v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -578,6 +589,163 @@ __device__ __forceinline__ void evaluate_tiles(const Params &p, WGShared &S, flo
     __syncthreads();
 }
 
+// The same partial for fits of three or more members with the Gram sums on
+// the matrix cores.  The tile of [J r] rows is formed in LDS exactly as above.
+// Wave w then takes pixel rows 64w .. 64w+63 of the tile and accumulates
+// G = X^T X over them with v_mfma_f32_16x16x4f32 (four pixels per
+// instruction), one 16 x 16 block per pair of 16-column groups (bi >= bj) of
+// X; columns past n are read as zeros.  A tile's FP32 block sums are added
+// into FP64 accumulators, so the sums across tiles lose nothing.  At the end
+// the four waves' FP64 sums are added through LDS in a fixed order:
+// (w0 + w2) + (w1 + w3).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int NB>
+__device__ void evaluate_tiles_mfma(const Params &p, WGShared &S, float *tile, int64_t tile0,
+                                    int64_t stride, double *out)
+{
+    constexpr int NBL = NB * (NB + 1) / 2;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int m = S.m, n = S.n, C = n + 1;
+    const int n_out = C * (C + 1) / 2;
+    double g[NBL][4];
+#pragma unroll
+    for (int q = 0; q < NBL; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[q][r] = 0.0;
+
+    const int64_t total = S.pref[m];
+    const int64_t ntiles = (total + kT - 1) / kT;
+    double npx = 0.0, f_acc = 0.0, c_acc = 0.0;
+    float *row = tile + t * kTileStride;
+    // This thread's pixel of tile ti: coordinates, whether it is a first
+    // occurrence in U, and its residual value (loaded one tile ahead).
+    auto locate = [&](int64_t ti, int32_t &r, int32_t &c, bool &valid, float &rv) {
+        const int64_t lin = ti * kT + t;
+        valid = false;
+        r = 0;
+        c = 0;
+        rv = 0.0f;
+        if (ti >= ntiles || lin >= total) return;
+        int w = 0;
+        while (lin >= S.pref[w + 1]) ++w;
+        // a window lies inside the image (fewer than 2^32 pixels): 32-bit division
+        const uint32_t local = (uint32_t)(lin - S.pref[w]);
+        const uint32_t wc = (uint32_t)(S.win[w][3] - S.win[w][2] + 1);
+        r = S.win[w][0] + (int32_t)(local / wc);
+        c = S.win[w][2] + (int32_t)(local % wc);
+        valid = true;
+        for (int i = 0; i < w; ++i)
+            if (in_box(S.win[i], r, c)) { valid = false; break; }
+        if (valid) rv = p.R[(int64_t)r * p.W + c];
+    };
+    int32_t nr_, nc_;
+    bool nvalid;
+    float nrv;
+    locate(tile0, nr_, nc_, nvalid, nrv);
+    const int kr = lane >> 4, cc = lane & 15;
+    for (int64_t ti = tile0; ti < ntiles; ti += stride) {
+        const int32_t r = nr_, c = nc_;
+        const bool valid = nvalid;
+        const float rv = nrv;
+        locate(ti + stride, nr_, nc_, nvalid, nrv);
+        if (valid) {
+            npx += 1.0;
+            double D = (double)rv;
+            const double cd = (double)c, rd = (double)r;
+            for (int j = 1; j < m; ++j) {
+                if (!in_box(S.wold[j], r, c)) continue;
+                const double dx = cd - S.ox[j], dy = rd - S.oy[j];
+                D += S.oamp[j] * exp(-(dx * dx + dy * dy) * S.oinv2[j]);
+            }
+            double M = 0.0;
+            for (int j = 0; j < m; ++j) {
+                float *J = row + 4 * j;
+                if (!in_box(S.win[j], r, c)) { J[0] = J[1] = J[2] = J[3] = 0.0f; continue; }
+                const double dx = cd - S.mx[j], dy = rd - S.my[j];
+                const double q = dx * dx + dy * dy;
+                const double e = exp(-q * S.minv2[j]);
+                const double G = S.mamp[j] * e;
+                M += G;
+                J[0] = (float)e;
+                J[1] = (float)(G * dx * S.minvs2[j]);
+                J[2] = (float)(G * dy * S.minvs2[j]);
+                J[3] = (float)(G * q * S.minvs3[j]);
+            }
+            const double res = D - M;
+            row[n] = (float)res;
+            f_acc += M * (M - 2.0 * D);
+            c_acc += res * res;
+        } else {
+            for (int k = 0; k <= n; ++k) row[k] = 0.0f;
+        }
+        __syncthreads();
+        f32x4 acc[NBL];
+#pragma unroll
+        for (int q = 0; q < NBL; ++q) acc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+        for (int ks = 0; ks < 16; ++ks) {
+            const float *xr = tile + (wave * 64 + ks * 4 + kr) * kTileStride;
+            float x[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int col = b * 16 + cc;
+                x[b] = col < C ? xr[col] : 0.0f;
+            }
+            int q = 0;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = 0; bj <= bi; ++bj, ++q)
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[bi], x[bj], acc[q], 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < NBL; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) g[q][r] += (double)acc[q][r];
+        __syncthreads();                   // the tile is rewritten next
+    }
+    // Lane l of wave w holds, for block (bi, bj), the entries of rows
+    // 16 bi + 4 (l / 16) + r and column 16 bj + l % 16 of G.  Entry (i, k),
+    // i <= k, of the output is G[k][i], taken from block (k / 16, i / 16).
+    double *buf = reinterpret_cast<double *>(tile);
+    static_assert(2 * sizeof(double) * (kMaxN + 1) * (kMaxN + 2) / 2 <= kTileBytes, "wave sums");
+    for (int half = 0; half < 2; ++half) {
+        if ((wave >> 1) == half) {
+            double *dst = buf + (wave & 1) * n_out;
+            int q = 0;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = 0; bj <= bi; ++bj, ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int k = 16 * bi + 4 * kr + r, i = 16 * bj + cc;
+                        if (k < C && i <= k) {
+                            const int o = i * C - i * (i - 1) / 2 + (k - i);
+                            dst[o] = half ? dst[o] + g[q][r] : g[q][r];
+                        }
+                    }
+        }
+        __syncthreads();
+    }
+    for (int o = t; o < n_out; o += kT) out[o] = buf[o] + buf[n_out + o];
+    // F, chi2 and the pixel count: wave sums, then the four waves in order
+    const double f_w = wave_sum(f_acc), c_w = wave_sum(c_acc), p_w = wave_sum(npx);
+    if (lane == 0) {
+        S.wsum[wave][0] = f_w;
+        S.wsum[wave][1] = c_w;
+        S.wsum[wave][2] = p_w;
+    }
+    __syncthreads();
+    if (t < 3) {
+        double v = 0.0;
+        for (int w = 0; w < kT / 64; ++w) v += S.wsum[w][t];
+        out[n_out + t] = v;
+    }
+    __syncthreads();
+}
+
 // The same partial for fits of at most two members (n <= 8): each thread keeps
 // the 15 or 45 Gram entries of its own pixels in registers, with no barrier per
 // tile.  J and r are FP32 values; their products are exact in FP64 and are
@@ -586,25 +754,31 @@ __device__ __forceinline__ void evaluate_tiles(const Params &p, WGShared &S, flo
 // combined once at the end by wave shuffles and the four waves in order.
 template <int M>
 __device__ __forceinline__ void evaluate_tiles_reg(const Params &p, WGShared &S, int64_t tile0, int64_t stride,
-                                   double *out)
+                                   double *out, float *stage)
 {
     constexpr int N = 4 * M, C = N + 1, NO = C * (C + 1) / 2;
     const int t = threadIdx.x;
+    const int64_t total = S.pref[M];
+    const int64_t ntiles = (total + kT - 1) / kT;
+    // This thread's pixel of tile ti (row-major within the window it falls in).
+    auto locate = [&](int64_t lin, int &w, int32_t &r, int32_t &c) {
+        w = (M > 1 && lin >= S.pref[1]) ? 1 : 0;
+        // a window lies inside the image (fewer than 2^32 pixels): 32-bit division
+        const uint32_t local = (uint32_t)(lin - S.pref[w]);
+        const uint32_t wc = (uint32_t)(S.win[w][3] - S.win[w][2] + 1);
+        r = S.win[w][0] + (int32_t)(local / wc);
+        c = S.win[w][2] + (int32_t)(local % wc);
+    };
     double acc[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) acc[o] = 0.0;
     double npx = 0.0, f_acc = 0.0, c_acc = 0.0;
-    const int64_t total = S.pref[M];
-    const int64_t ntiles = (total + kT - 1) / kT;
     for (int64_t ti = tile0; ti < ntiles; ti += stride) {
         const int64_t lin = ti * kT + t;
         if (lin >= total) continue;
-        const int w = (M > 1 && lin >= S.pref[1]) ? 1 : 0;
-        // a window lies inside the image (fewer than 2^32 pixels): 32-bit division
-        const uint32_t local = (uint32_t)(lin - S.pref[w]);
-        const uint32_t wc = (uint32_t)(S.win[w][3] - S.win[w][2] + 1);
-        const int32_t r = S.win[w][0] + (int32_t)(local / wc);
-        const int32_t c = S.win[w][2] + (int32_t)(local % wc);
+        int w;
+        int32_t r, c;
+        locate(lin, w, r, c);
         if (M > 1 && w == 1 && in_box(S.win[0], r, c)) continue;
         npx += 1.0;
         double D = (double)p.R[(int64_t)r * p.W + c];
@@ -645,22 +819,44 @@ __device__ __forceinline__ void evaluate_tiles_reg(const Params &p, WGShared &S,
             for (int k = i; k < C; ++k, ++o) acc[o] = fma(cold[i], cold[k], acc[o]);
     }
     const int lane = t & 63, wave = t >> 6;
+    // Wave sums of the Gram entries, F, chi2 and the pixel count, through the
+    // tile buffer (idle in this path): each wave writes its lanes' values,
+    // half of them at a time, and lane q then adds value q over the 64 lanes
+    // in lane order.  Rows are padded to 65 doubles against bank conflicts.
+    constexpr int NV = NO + 3, HALF = (NV + 1) / 2, ROW = 65;
+    static_assert(sizeof(double) * (kT / 64) * HALF * ROW <= kTileBytes, "reduction buffer");
+    double v[NV];
 #pragma unroll
-    for (int o = 0; o < NO; ++o) {
-        const double v = wave_sum(acc[o]);
-        if (lane == 0) S.wred[wave][o] = v;
-    }
-    const double f_w = wave_sum(f_acc), c_w = wave_sum(c_acc), p_w = wave_sum(npx);
-    if (lane == 0) {
-        S.wred[wave][NO] = f_w;
-        S.wred[wave][NO + 1] = c_w;
-        S.wred[wave][NO + 2] = p_w;
+    for (int o = 0; o < NO; ++o) v[o] = acc[o];
+    v[NO] = f_acc;
+    v[NO + 1] = c_acc;
+    v[NO + 2] = npx;
+    double *buf = reinterpret_cast<double *>(stage) + wave * (HALF * ROW);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int q = 0; q < HALF; ++q)
+            if (h * HALF + q < NV) buf[q * ROW + lane] = v[h * HALF + q];
+        wave_lds_sync();
+        if (lane < HALF && h * HALF + lane < NV) {
+            // four interleaved chains over the lanes, added in a fixed order
+            const double *row = buf + lane * ROW;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            for (int l = 0; l < 16; ++l) {
+                s0 += row[l];
+                s1 += row[l + 16];
+                s2 += row[l + 32];
+                s3 += row[l + 48];
+            }
+            S.wred[wave][h * HALF + lane] = (s0 + s1) + (s2 + s3);
+        }
+        wave_lds_sync();                   // the buffer is rewritten by the next half
     }
     __syncthreads();
     if (t < NO + 3) {
-        double v = 0.0;
-        for (int wv = 0; wv < kT / 64; ++wv) v += S.wred[wv][t];
-        out[t] = v;
+        double tot = 0.0;
+        for (int wv = 0; wv < kT / 64; ++wv) tot += S.wred[wv][t];
+        out[t] = tot;
     }
     __syncthreads();
 }
@@ -1113,8 +1309,12 @@ __device__ __forceinline__ void commit(const Params &p, WGShared &S)
 __device__ __forceinline__ void evaluate_row(const Params &p, WGShared &S, float *tile, double *red, int64_t tile0,
                              int64_t stride, double *row)
 {
-    if (S.m == 1) evaluate_tiles_reg<1>(p, S, tile0, stride, row);
-    else if (S.m == 2) evaluate_tiles_reg<2>(p, S, tile0, stride, row);
+    if (S.m == 1) evaluate_tiles_reg<1>(p, S, tile0, stride, row, tile);
+    else if (S.m == 2) evaluate_tiles_reg<2>(p, S, tile0, stride, row, tile);
+    else if (S.m <= 3) evaluate_tiles_mfma<1>(p, S, tile, tile0, stride, row);
+    else if (S.m <= 7) evaluate_tiles_mfma<2>(p, S, tile, tile0, stride, row);
+    else if (S.m <= 11) evaluate_tiles_mfma<3>(p, S, tile, tile0, stride, row);
+    else if (S.m <= 15) evaluate_tiles_mfma<4>(p, S, tile, tile0, stride, row);
     else evaluate_tiles(p, S, tile, red, tile0, stride, row);
 }
 

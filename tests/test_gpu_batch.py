@@ -128,3 +128,21 @@ def test_batch_rejects_bad_team_size():
     with pytest.raises(asp.AspError):
         b.config(team_size=3)
     b.close()
+
+
+def test_batch_leader_working_alone_for_seconds():
+    """A 64 x 64 field with a team of 8: its leader scans, fits and updates
+    alone (every trial is at most 16 tiles, under solo_tiles 32), so its
+    followers get no command for the whole run, well past the 2 s bound of a
+    wait.  Their waits restart on the leader's per-iteration heartbeat, so the
+    field does not fail."""
+    f = skygen.make_batch_field(64, 7300, 20000)
+    b = asp.Batch([(f.dirty, f.psf, f.gain, 0.0)], max_iter=20000, max_active=5)
+    b.config(team_size=8, solo_tiles=32)
+    rep = b.run(12000)
+    print("solo leader run", rep, flush=True)
+    assert rep["fields_failed"] == 0
+    k, L = b.field(0).counts()
+    assert k == 12000
+    assert rep["ms"] > 2500, "the run must outlast the 2 s bound of a wait"
+    b.close()
