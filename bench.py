@@ -202,7 +202,8 @@ def full_run_leg(args, f, torch, asp):
     n = f.max_iter
     d_dirty, d_psf = device_field(f, torch)
     ctx = asp.Context(d_dirty, d_psf, f.gain, f.threshold, max_iter=n + args.full_samples,
-                      max_active=f.max_active)
+                      max_active=f.max_active, fit_solo_tiles=args.solo_tiles,
+                      fit_min_tiles=args.min_tiles, fit_group=args.group)
     del d_dirty, d_psf
     torch.cuda.synchronize()
     prof0 = ctx.fit_profile()

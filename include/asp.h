@@ -115,7 +115,7 @@ typedef struct {
     int32_t capacity;            /* component list size; 0 = max_iter            */
     int32_t fit_solo_tiles;      /* LM trials over at most this many 256-pixel
                                     tiles are evaluated by one work-group;
-                                    0 = default (8), -1 = never                  */
+                                    0 = default (16), -1 = never                 */
     int32_t fit_min_tiles;       /* least tiles per work-group when a trial is
                                     shared over the GPU; 0 = default (2)         */
     int32_t fit_group;           /* work-groups per first-level arrival counter of

@@ -65,6 +65,7 @@ struct WGShared {
     // LM state (work-group 0)
     double th_c[kMaxN], th_e[kMaxN], g_c[kMaxN], lo[kMaxN], hi[kMaxN], th0[kMaxN], th_old[kMaxN];
     double dd[kMaxN], rhs[kMaxN], rhs_copy[kMaxN], delta[kMaxN];
+    double ldiag[kMaxN];           // L_kk of the work-group Cholesky
     int32_t frozen[kMaxN];
     double F_c, chi2_c, mu, nu, pred, chi2_init, peak;
     int32_t trials, trials_total, converged, used_fallback, use_prop, pass, phase;
@@ -905,43 +906,58 @@ __device__ __forceinline__ void reduce_partials(const Params &p, WGShared &S, in
     __syncthreads();
 }
 
-// Work-group Cholesky solve of A x = b (A n x n in LDS, overwritten).
+// Work-group Cholesky solve of A x = b (A n x n in LDS, overwritten; b
+// overwritten), n <= 64, in the textbook arithmetic: L_kk = sqrt(d_k),
+// L_ik = A_ik / L_kk, A_ij -= L_ik L_jk, then the two triangular solves with
+// divisions by L_kk.  Column k of L is written into row k of the upper
+// triangle (U[k][i] = L[i][k]); the diagonal keeps the pivots d_k and the
+// L_kk go to S.ldiag.  Every thread takes the square root itself, so a column
+// costs two barriers (after the scaled column, after the trailing update,
+// which the threads share as a 16 x 16 grid).  The triangular solves run on
+// wave 0, one lane per row, with no barrier.
 __device__ bool chol_solve(WGShared &S, double *A, int n, double *b, double *x)
 {
-    const int t = threadIdx.x;
+    static_assert(kMaxN <= 64, "one lane per row in the triangular solves");
+    static_assert(kT == 256, "a 16 x 16 thread grid");
+    const int t = threadIdx.x, ti = t >> 4, tj = t & 15;
     for (int k = 0; k < n; ++k) {
-        if (t == 0) {
-            const double d = A[k * n + k];
-            S.ok = (d > 0.0 && isfinite(d)) ? 1 : 0;
-            if (S.ok) A[k * n + k] = sqrt(d);
-        }
+        const double d = A[k * n + k];
+        if (!(d > 0.0 && isfinite(d))) return false;     // the same for every thread
+        const double l = sqrt(d);
+        for (int i = k + 1 + t; i < n; i += kT) A[k * n + i] = A[i * n + k] / l;
+        if (t == 0) S.ldiag[k] = l;
         __syncthreads();
-        if (!S.ok) return false;
-        for (int i = k + 1 + t; i < n; i += kT) A[i * n + k] /= A[k * n + k];
-        __syncthreads();
-        const int rem = n - k - 1;
-        for (int e = t; e < rem * rem; e += kT) {
-            const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-            if (j <= i) A[i * n + j] -= A[i * n + k] * A[j * n + k];
+        const double *Lk = A + k * n;                    // L[i][k] = Lk[i], i > k
+        for (int i = k + 1 + ti; i < n; i += 16) {
+            const double lik = Lk[i];
+            for (int j = k + 1 + tj; j <= i; j += 16) A[i * n + j] -= lik * Lk[j];
         }
         __syncthreads();
     }
-    for (int i = 0; i < n; ++i) {
-        if (t == 0) x[i] = b[i] / A[i * n + i];
-        __syncthreads();
-        for (int j = i + 1 + t; j < n; j += kT) b[j] -= A[j * n + i] * x[i];
-        __syncthreads();
-    }
-    for (int i = n - 1; i >= 0; --i) {
-        if (t == 0) x[i] = x[i] / A[i * n + i];
-        __syncthreads();
-        for (int j = t; j < i; j += kT) x[j] -= A[i * n + j] * x[i];
-        __syncthreads();
-    }
-    if (t == 0) {
-        int good = 1;
-        for (int i = 0; i < n; ++i) good &= isfinite(x[i]) ? 1 : 0;
-        S.ok = good;
+    if (t < 64) {
+        const int lane = t;
+        // L y = b, with L[j][i] = A[i][j] for j > i
+        for (int i = 0; i < n; ++i) {
+            wave_lds_sync();
+            const double yi = b[i] / S.ldiag[i];
+            const int j = i + 1 + lane;
+            if (j < n) b[j] -= A[i * n + j] * yi;
+            if (lane == 0) x[i] = yi;
+        }
+        // L^T x = y, with L[i][j] = A[j][i] for j < i
+        for (int i = n - 1; i >= 0; --i) {
+            wave_lds_sync();
+            const double xi = x[i] / S.ldiag[i];
+            wave_lds_sync();                 // x[i] is read by every lane before it is rewritten
+            if (lane == 0) x[i] = xi;
+            for (int j = lane; j < i; j += 64) x[j] -= A[j * n + i] * xi;
+        }
+        wave_lds_sync();
+        if (lane == 0) {
+            int good = 1;
+            for (int i = 0; i < n; ++i) good &= isfinite(x[i]) ? 1 : 0;
+            S.ok = good;
+        }
     }
     __syncthreads();
     return S.ok != 0;
@@ -1151,24 +1167,31 @@ __device__ __forceinline__ void lm_step(const Params &p, WGShared &S, double *H2
             if (S.trials >= p.lm_max_iter) S.finished = 1;
             else S.trials++;
         }
-        if (t < n) {
-            double dmax = 0.0;
-            for (int i = 0; i < n; ++i) dmax = Hc[i * n + i] > dmax ? Hc[i * n + i] : dmax;
-            const double d = Hc[t * n + t];
-            S.dd[t] = d < 1e-12 * dmax ? 1e-12 * dmax : d;
-            const double th = S.th_c[t], g = S.g_c[t];
-            S.frozen[t] = ((th <= S.lo[t] && g <= 0.0) || (th >= S.hi[t] && g >= 0.0)) ? 1 : 0;
-            S.rhs[t] = S.frozen[t] ? 0.0 : g;
+        if (t < 64) {
+            // the largest diagonal entry: a max over the lanes of wave 0
+            double dmax = t < n ? Hc[t * n + t] : 0.0;
+            for (int off = 32; off > 0; off >>= 1) {
+                const double o = __shfl_xor(dmax, off, 64);
+                dmax = o > dmax ? o : dmax;
+            }
+            if (t < n) {
+                const double d = Hc[t * n + t];
+                S.dd[t] = d < 1e-12 * dmax ? 1e-12 * dmax : d;
+                const double th = S.th_c[t], g = S.g_c[t];
+                S.frozen[t] = ((th <= S.lo[t] && g <= 0.0) || (th >= S.hi[t] && g >= 0.0)) ? 1 : 0;
+                S.rhs[t] = S.frozen[t] ? 0.0 : g;
+            }
         }
         __syncthreads();
         if (S.finished) break;
         const double mu = S.mu;
-        for (int e = t; e < n * n; e += kT) {
-            const int i = e / n, k = e % n;
-            double v;
-            if (S.frozen[i] || S.frozen[k]) v = (i == k) ? 1.0 : 0.0;
-            else v = Hc[e] + (i == k ? mu * S.dd[i] : 0.0);
-            A[e] = v;
+        for (int i = t >> 4; i < n; i += 16) {
+            for (int k = t & 15; k < n; k += 16) {
+                double v;
+                if (S.frozen[i] || S.frozen[k]) v = (i == k) ? 1.0 : 0.0;
+                else v = Hc[i * n + k] + (i == k ? mu * S.dd[i] : 0.0);
+                A[i * n + k] = v;
+            }
         }
         if (t < n) S.rhs_copy[t] = S.rhs[t];
         __syncthreads();

@@ -428,7 +428,7 @@ asp_status create_common(const float *dirty, bool dirty_dev, int64_t H, int64_t 
     P.lm_tol = opt.lm_tol;
     P.use_proposal = 1;
     P.fit_grid = fit_grid;
-    P.solo_tiles = opt.fit_solo_tiles == 0 ? 8 : opt.fit_solo_tiles;
+    P.solo_tiles = opt.fit_solo_tiles == 0 ? 16 : opt.fit_solo_tiles;
     P.min_tiles = opt.fit_min_tiles == 0 ? 2 : opt.fit_min_tiles;
     P.spin_ticks = spin_limit_ticks(c->device);
     P.group = opt.fit_group == 0 ? 16 : opt.fit_group;
