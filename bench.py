@@ -687,7 +687,7 @@ def bench_batch(args):
     log(f"batched: {rep} in {secs:.3f}s -> {value:.0f} iterations/s")
     b.close()
     seq_secs, seq_iter = 0.0, 0
-    for f in fields:
+    for i, f in enumerate(fields):
         ctx = asp.Context(f.dirty, f.psf, f.gain, f.threshold, max_iter=5000, max_active=5)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -696,6 +696,9 @@ def bench_batch(args):
         seq_secs += time.perf_counter() - t1
         seq_iter += r["iterations"]
         ctx.close()
+        if (i + 1) % 8 == 0:
+            log(f"sequential: {i + 1} of {len(fields)} fields, {seq_iter} iterations in "
+                f"{seq_secs:.1f}s")
     seq = seq_iter / seq_secs
     log(f"sequential: {seq_iter} iterations in {seq_secs:.3f}s -> {seq:.0f} iterations/s")
     line = {
