@@ -1379,6 +1379,84 @@ __device__ __forceinline__ void arrive(const Params &p, FitGlobal *G, WGShared &
     if (t == 0) __hip_atomic_fetch_add(&G->top, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Flat arrival of a shared trial of at most eight parameters (k_fit only):
+// every work-group, work-group 0 included, adds itself to its group's counter
+// with one release and leaves; no group sums its rows.  Work-group 0 waits for
+// every group (flat_wait), resets the counters, and sums all the evaluated rows
+// itself (reduce_flat), in the association of the two-level sums: rows in
+// order within a group of p.group, then the groups in order.
+constexpr int kFlatMaxN = 8;
+static_assert(sizeof(double) * ((kFlatMaxN + 1) * (kFlatMaxN + 2) / 2 + 3) * kMaxGroups <=
+                  kTileBytes, "group sums of the flat reduction in the tile buffer");
+__device__ __forceinline__ void arrive_flat(FitGlobal *G, int wg, int gs)
+{
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(&G->arrive_g[wg / gs], 1u, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Work-group 0: lane g of wave 0 polls group g's counter until the group is
+// complete (every group of the grid, evaluating or not, so that no late
+// arrival can count toward the next trial), then clears it.  Bounded in time.
+__device__ __forceinline__ bool flat_wait(FitGlobal *G, WGShared &S, int nwg, int gs,
+                                          unsigned long long limit)
+{
+    const int t = threadIdx.x;
+    const int ngroups = (nwg + gs - 1) / gs;
+    if (t < 64) {
+        const int g = t;
+        const bool live = g < ngroups;
+        const unsigned need = live ? (unsigned)((g + 1) * gs < nwg ? gs : nwg - g * gs) : 0u;
+        const unsigned long long t0 = now_ticks();
+        bool ok = true;
+        for (;;) {
+            const unsigned v = live ? __hip_atomic_load(&G->arrive_g[g], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)
+                                    : 0u;
+            if (__all(v >= need)) break;
+            if (now_ticks() - t0 > limit) { ok = false; break; }
+            __builtin_amdgcn_s_sleep(kPollSleep);
+        }
+        if (live) __hip_atomic_store(&G->arrive_g[g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t == 0) S.abort = ok ? 0 : 1;
+    }
+    __syncthreads();
+    return S.abort == 0;
+}
+
+// The evaluated rows 0 .. geff-1 summed into He, S.ge, S.Fe, S.chi2e, S.npx_e
+// with the two-level association; `scratch` holds the group sums
+// ((n_out + 3) x groups doubles, LDS).
+__device__ __forceinline__ void reduce_flat(const Params &p, WGShared &S, int geff, int gs,
+                                            double *He, double *scratch)
+{
+    const int n = S.n;
+    const int n_out = (n + 1) * (n + 2) / 2, nv = n_out + 3;
+    const int ng = (geff + gs - 1) / gs;
+    for (int e = threadIdx.x; e < nv * ng; e += kT) {
+        const int o = e % nv, g = e / nv;
+        const int r0 = g * gs, r1 = r0 + gs < geff ? r0 + gs : geff;
+        scratch[g * nv + o] = sum_column(p, r0, r1, o);
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < nv; o += kT) {
+        double v = scratch[o];
+        for (int g = 1; g < ng; ++g) v += scratch[g * nv + o];
+        if (o >= n_out) {
+            if (o == n_out) S.Fe = v;
+            else if (o == n_out + 1) S.chi2e = v;
+            else S.npx_e = (int64_t)v;
+            continue;
+        }
+        int i, k;
+        out_pair(o, n, i, k);
+        if (i < n && k < n) { He[i * n + k] = v; He[k * n + i] = v; }
+        else if (i < n) S.ge[i] = v;
+    }
+    __syncthreads();
+}
+
 // The peak and the stop test (Sect. 2 steps 1 and 4) of one fit, thread 0 of
 // the leading work-group: sets S.idx, S.peak, S.stop and the fit's
 // bookkeeping.  `abort` reports a wait that ran out before it.
@@ -1449,6 +1527,20 @@ __device__ __forceinline__ bool trial_eval(const Params &p, FitGlobal *G, WGShar
     publish(G);
     evaluate_row(p, S, tile, red, 0, geff, p.partials);
     lap(p, S, kPEval);
+    if (cmd == 0 && S.n <= kFlatMaxN) {
+        arrive_flat(G, 0, p.group);
+        lap(p, S, kPArrive);
+        const bool ok = flat_wait(G, S, nwg, p.group, p.spin_ticks);
+        lap(p, S, kPWait);
+        if (!ok) {
+            if (t == 0) st->stop = ASP_ERR_DEVICE;
+            __syncthreads();
+            return false;
+        }
+        reduce_flat(p, S, geff, p.group, He, reinterpret_cast<double *>(tile));
+        lap(p, S, kPReduce);
+        return true;
+    }
     arrive(p, G, S, 0, nwg, geff, false);
     lap(p, S, kPArrive);
     if (t == 0) {
@@ -1580,7 +1672,8 @@ __global__ __launch_bounds__(kT) void k_fit(Params p)
             const int geff = eval_groups(ntiles, nwg, p.min_tiles);
             if (wg < geff)
                 evaluate_row(p, S, tile, red, wg, geff, p.partials + (int64_t)wg * kPartStride);
-            arrive(p, G, S, wg, nwg, geff, false);
+            if (S.n <= kFlatMaxN) arrive_flat(G, wg, p.group);
+            else arrive(p, G, S, wg, nwg, geff, false);
         }
     }
 
