@@ -84,7 +84,8 @@ typedef struct {
     int32_t members[ASP_MAX_ACTIVE];
     int32_t lm_iters;            /* LM trials used (both fits if a fallback ran) */
     int32_t converged;
-    int32_t used_fallback;       /* learned proposal failed; simple values used  */
+    int32_t used_fallback;       /* the proposal's fit failed (no convergence or
+                                    a zero amplitude); simple values fitted     */
     int64_t idx;                 /* peak pixel                                   */
     float peak;                  /* residual at the peak before the fit          */
     float pad;
@@ -210,8 +211,9 @@ asp_status asp_find_peak(asp_ctx *ctx, int64_t *idx, float *value);
  * learned mode; otherwise init is a proposal in convolved space (clamped to
  * the peak's sign, s >= omega_b and 16 px of the peak).  With a proposal the
  * objective is evaluated at it and at the simple values and LM starts from the
- * lower; if it started from the proposal and does not converge, the simple
- * values are fitted instead.  The active set depends on idx and the component
+ * lower; if it started from the proposal and does not converge, or converges
+ * to a new component of amplitude zero, the simple values are fitted instead.
+ * The active set depends on idx and the component
  * list only.  Must follow asp_find_peak.  rep may be NULL.  Returns ASP_OK or
  * ASP_LM_NOT_CONVERGED.
  */
@@ -387,7 +389,8 @@ asp_status asp_fit_histogram(asp_ctx *ctx, int64_t *fits, int64_t *trials, doubl
  * c*-16..c*+15, zero outside the image, divided by R[p*]) to
  * (a / R[p*], log(s / omega_b), x - c*, y - r*) of the new component, which
  * replaces the simple initial values of Sect. 3 as the start of the LM fit;
- * when that fit does not converge the simple values are fitted instead.
+ * when that fit does not converge, or ends with a new component of amplitude
+ * zero, the simple values are fitted instead.
  * Weights are FP32 in the order W1 (256 x 1024, row-major), b1, W2
  * (256 x 256), b2, W3 (4 x 256), b3: ASP_MLP_PARAMS values.
  */
