@@ -6,8 +6,9 @@ module.  It shares no code with the HIP library.
 The proposal replaces the simple initial values of Sect. 3 (the residual peak
 and the main-lobe width) for the new component of a fit.  A multilayer
 perceptron maps the residual patch around the peak to a start point; the LM fit
-of Sect. 3 then runs from it and remains the judge: if that fit does not
-converge, the simple values are fitted instead.
+of Sect. 3 then runs from it and decides whether the proposal is kept: if that
+fit does not converge, or ends with a new component of amplitude zero, the
+simple values are fitted instead (that rule lives in the C oracle's step).
 
 Network (sizes ``dims = (d0, d1, d2, d3)``, by default (1024, 256, 256, 4)):
     h1 = relu(W1 x + b1),  h2 = relu(W2 h1 + b2),  y = W3 h2 + b3,

@@ -2,8 +2,9 @@
 // the residual patch around the peak to the start point of the new
 // component's fit, in place of the simple initial values of Sect. 3 (the
 // residual peak and the main-lobe width).  The LM fit of Sect. 3 runs from the
-// proposal and stays the judge: when that fit does not converge, the fit
-// kernel fits the simple values instead.
+// proposal and decides whether it is kept: when that fit does not converge,
+// or ends with a new component of amplitude zero, the fit kernel fits the
+// simple values instead.
 //
 // Network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3.
 //   x = the 32 x 32 patch around the peak pixel (r*, c*), rows r*-16..r*+15,
