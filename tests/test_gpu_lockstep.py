@@ -125,3 +125,29 @@ def test_lockstep_c1024_sampled():
         rec = ls.step()
         ls.check(rec, strict=rec["gpu_conv"] and rec["orc_conv"])
     ctx.close()
+
+
+@pytest.mark.parametrize("name,target,steps", [("c1024", 4000, 4), ("c1024", 4990, 4),
+                                               ("c4096", 12000, 3)])
+def test_lockstep_late_iterations(name, target, steps):
+    """Lockstep deep into the configured runs (the 1024^2 field's 5000
+    iterations, the 4096^2 field's 20000): the device runs to the target
+    iteration on its own, then the oracle is loaded with its state and both
+    step together."""
+    f = skygen.make_c1024(1000) if name == "c1024" else skygen.make_c4096(4096)
+    print("lockstep", name, "from iteration", target, flush=True)
+    ctx = make_ctx(f)
+    rc, rep = ctx.run(target)
+    assert rc == asp.ASP_OK and rep["iterations"] == target
+    ls = Lockstep(ctx, f)
+    n_strict = 0
+    for it in range(steps):
+        rec = ls.step()
+        assert rec is not None
+        strict = rec["gpu_conv"] and rec["orc_conv"]
+        print(f"k={rec['k']} members {rec['members']} conv {rec['gpu_conv']}/{rec['orc_conv']} "
+              f"resid {rec['resid_err']:.3g} cond {rec['cond']:.3g}", flush=True)
+        ls.check(rec, strict=strict)
+        n_strict += strict
+    assert n_strict >= 1
+    ctx.close()
