@@ -25,13 +25,17 @@ def make_batch(fields, **kw):
                      max_iter=fields[0].max_iter, max_active=5, **kw)
 
 
-def batch_lockstep(fields, team, n_iter, min_strict):
+def batch_lockstep(fields, team, n_iter, min_strict, pre_iters=0):
     """One iteration per launch; each field's oracle is loaded with the field's
     pre-launch state and steps once.  Peak, members (from the device's report
     of the field's last fit), whether the new component joined, the committed
-    list and the residual are compared."""
+    list and the residual are compared.  pre_iters: batched iterations run
+    first, without comparison."""
     b = make_batch(fields)
     b.config(team_size=team)
+    if pre_iters:
+        rep = b.run(pre_iters)
+        assert rep["fields_failed"] == 0 and rep["iterations"] == pre_iters * len(fields)
     print("batch config", b.get_config(), [f.shape for f in fields], flush=True)
     ctxs = [b.field(i) for i in range(len(fields))]
     orcs = []
@@ -80,6 +84,13 @@ def test_batch_lockstep_large_fields():
     trials and shared updates on every field."""
     fields = [skygen.make_batch_field(n, 7100 + i, 400) for i, n in enumerate([2048, 1024, 256])]
     batch_lockstep(fields, 32, 4, 9)
+
+
+def test_batch_lockstep_late_in_the_run():
+    """The same comparison after 1500 batched iterations per field, on fields of
+    2048^2, 1024^2 and 512^2 with a team of 16 work-groups."""
+    fields = [skygen.make_batch_field(n, 7400 + i, 2000) for i, n in enumerate([2048, 1024, 512])]
+    batch_lockstep(fields, 16, 3, 3, pre_iters=1500)
 
 
 def test_batch_replays_keep_invariants():
