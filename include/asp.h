@@ -461,8 +461,8 @@ asp_status asp_refresh_residual(asp_ctx *ctx);
  *      omega_b^2, 0), F_0 = a s^2 / (alpha_b omega_b^2);
  *   3. Levenberg-Marquardt fit of the one new component theta = (F, x, y,
  *      v = omega^2) against chi^2 = || R - B (*) g(theta) ||^2 over the whole
- *      image with the true PSF B, convolved by FFT (FP64) in every
- *      evaluation.  g is the unit-flux component rendered as
+ *      image with the true PSF B, convolved in FP64 in every evaluation (by
+ *      FFT or directly, asp_set_2004_convolution).  g is the unit-flux component rendered as
  *      asp_refresh_residual renders the model, times F; the squared width
  *      keeps the objective differentiable at a point source.  Bounds: F keeps
  *      the start's sign, x and y stay in the start's window,
@@ -487,13 +487,33 @@ typedef struct {
     int32_t trials;              /* LM trials                                    */
     int32_t converged;
     int32_t evaluations;         /* evaluations of Eq. 3 (trials + the start)    */
-    int32_t pad;
+    int32_t direct_evals;        /* of those, convolved directly (the rest by FFT)*/
     double start[4];             /* the smoothing start (a, x, y, s), convolved  */
     double theta0[4];            /* sky (F, x, y, omega^2) start in the bounds   */
     double theta[4];             /* fitted sky (F, x, y, omega^2), before gain   */
     double lo[4], hi[4];         /* the bounds                                   */
     double chi2_init, chi2_final;/* over the whole image                         */
+    int32_t direct_update;       /* 1: the update was convolved directly         */
+    int32_t pad;
 } asp_fit2004_report;
+
+/*
+ * How asp_step_2004 and asp_run_2004 form B (*) g (Sect. 2 step 3 and Eq. 3
+ * with the true PSF).  Every image the rendering makes is a sum of outer
+ * products of per-axis factors, so B (*) g is also a pass along the rows of
+ * the PSF with the column factors and one along the columns with the row
+ * factors, in FP64, with the same result up to rounding; its cost grows with
+ * the taps (12 per axis below omega = 1 px, 2 h + 1 above) where the FFTs'
+ * does not.  mode 0 (default): directly when its multiply-adds undercut a
+ * fixed count per padded FFT pixel, by the squared width of the point under
+ * evaluation (or, on padded grids of at most 1024^2 pixels, where four
+ * evaluations are queued per read, by its upper bound), else by FFT; 1: always
+ * by FFT; 2: directly.  The direct row pass keeps (H + nr - 1) x W rows per
+ * factor in the FFT grids (three factors for an evaluation, one for the
+ * update); where they would not fit, the FFT is used in every mode.
+ * ASP_ERR_INVALID_ARG for another mode.
+ */
+asp_status asp_set_2004_convolution(asp_ctx *ctx, int32_t mode);
 
 asp_status asp_step_2004(asp_ctx *ctx, asp_fit2004_report *rep);
 
@@ -605,9 +625,10 @@ asp_status asp_batch_autotune(asp_batch *batch, int64_t probe_iter, int32_t *tea
  * passes (column and row pass together), 5 the smoothing pick, 6 the
  * exact-PSF refresh (rendering, two FFTs, spectral product, subtraction),
  * 7 one evaluation of the Asp-Clean2004 objective (rendering of the component
- * and its derivatives, the batched FFTs, the sums, the LM decision; queued
- * evaluations past the end of a fit included), 8 the
- * Asp-Clean2004 update (rendering, two FFTs, subtraction, the new component).
+ * and its derivatives with the batched FFTs, or the factors with the two
+ * direct passes; the sums, the LM decision; queued evaluations past the end
+ * of a fit included), 8 the Asp-Clean2004 update (the convolution of either
+ * kind, subtraction, the new component).
  * Switching timing on or off clears the totals. */
 asp_status asp_kernel_timing(asp_ctx *ctx, int32_t on);
 asp_status asp_kernel_times(asp_ctx *ctx, double *ms, int64_t *launches, int32_t n);

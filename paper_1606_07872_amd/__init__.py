@@ -34,7 +34,7 @@ EXPORTS = ["asp_default_options", "asp_create", "asp_create_device", "asp_destro
            "asp_batch_run", "asp_batch_autotune", "asp_smooth_peak", "asp_smooth_map",
            "asp_smooth_widths", "asp_smooth_work", "asp_refresh_residual", "asp_step_2004",
            "asp_run_2004", "asp_model_image", "asp_state_size", "asp_save_state",
-           "asp_load_state"]
+           "asp_load_state", "asp_set_2004_convolution"]
 
 MLP_PARAMS = 329220
 MLP_IN = 1024
@@ -90,11 +90,12 @@ class FitReport(ctypes.Structure):
 class Fit2004Report(ctypes.Structure):
     _fields_ = [("idx", ctypes.c_int64), ("peak", ctypes.c_float), ("scale", ctypes.c_int32),
                 ("trials", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("evaluations", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("evaluations", ctypes.c_int32), ("direct_evals", ctypes.c_int32),
                 ("start", ctypes.c_double * 4), ("theta0", ctypes.c_double * 4),
                 ("theta", ctypes.c_double * 4), ("lo", ctypes.c_double * 4),
                 ("hi", ctypes.c_double * 4), ("chi2_init", ctypes.c_double),
-                ("chi2_final", ctypes.c_double)]
+                ("chi2_final", ctypes.c_double), ("direct_update", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class BatchReport(ctypes.Structure):
@@ -190,6 +191,7 @@ def lib():
         L.asp_save_state.argtypes = [vp, vp, i64, P(i64)]
         L.asp_load_state.argtypes = [vp, vp, i64]
         L.asp_run_2004.argtypes = [vp, i64, P(RunReport)]
+        L.asp_set_2004_convolution.argtypes = [vp, i32]
         for name in EXPORTS:
             if name not in ("asp_destroy", "asp_last_error", "asp_mlp_destroy",
                             "asp_mlp_last_error", "asp_batch_destroy", "asp_batch_last_error"):
@@ -455,6 +457,11 @@ class Context:
             v = getattr(rep, f)
             out[f] = np.array(v[:]) if isinstance(v, ctypes.Array) else v
         return rc, out
+
+    def set_2004_convolution(self, mode):
+        """How the 2004 path forms B (*) g: "auto" (0), "fft" (1) or "direct" (2)."""
+        code = {"auto": 0, "fft": 1, "direct": 2}.get(mode, mode)
+        self._check(lib().asp_set_2004_convolution(self._ctx, int(code)))
 
     def run_2004(self, n_iter: int):
         rep = RunReport()

@@ -325,6 +325,7 @@ struct A4State {
 };
 constexpr int kA4Sums = 16;        // 10 Gram entries, 4 of J^T r, F, chi2
 constexpr int kA4Blocks = 1024;    // partial rows of an evaluation
+constexpr int kA4RowBlocks = 2048; // work-groups of the direct convolution's row pass
 
 struct A4Args {
     float *R;
@@ -333,10 +334,16 @@ struct A4Args {
     double *ca, *cx, *cy, *cs;
     int64_t *c_added, *c_updated;
     int64_t cap;
-    double *grid;                  // 4 images Py x Px: g, dg/dx, dg/dy, dg/d(omega^2)
+    double *grid;                  // 4 images Py x Px: B(*) of g, dg/dx, dg/dy, dg/d(omega^2)
     double2 *spec;                 // their half spectra, Py x (Px/2 + 1) each
+    double2 *fac;                  // 1-D DFTs of the factors: 3 Py rows, then 3 (Px/2 + 1)
     const double2 *pspec;          // the PSF's
     double *partials;              // nblk x kA4Sums
+    const float *psf;              // the PSF, Hp x Wp (direct convolution)
+    double *taps;                  // per-axis factors: 3 W column taps, then 3 H row taps
+    int32_t *tapi;                 // C0, nc, R0, nr of the factors
+    int64_t grid_cap;              // doubles in grid (4 Py Px)
+    int64_t Hp, Wp;
     int64_t H, W, Py, Px;
     int32_t ci, cj;                // the PSF's peak pixel
     int32_t budget;
@@ -346,10 +353,17 @@ struct A4Args {
 // Stop test after the peak, the start from the smoothing method, bounds.
 hipError_t a4_begin(const A4Args &a, hipStream_t s);
 // One evaluation of Eq. 3 and its Jacobian at s->te, then the LM decision and
-// the next trial point (or done).  plan_fwd / plan_inv: batched (4) D2Z / Z2D.
-hipError_t a4_trial(const A4Args &a, void *plan_fwd4, void *plan_inv4, hipStream_t s);
-// The residual update R -= gain B (*) g(theta) and the new component.
-hipError_t a4_commit(const A4Args &a, void *plan_fwd, void *plan_inv, hipStream_t s);
+// the next trial point (or done).  plan_inv4: the batched (4) Z2D.
+hipError_t a4_trial(const A4Args &a, void *plan_inv4, hipStream_t s);
+// The residual update R -= gain B (*) g(theta) and the new component
+// (plan_inv: the single Z2D).
+hipError_t a4_commit(const A4Args &a, void *plan_inv, hipStream_t s);
+// The same two steps with B (*) g formed directly: a pass along the rows of the
+// PSF with the column factors into the grids (3 planes of (H + nr - 1) x W for
+// an evaluation, 1 for the update; the caller checks that they fit), then a
+// pass along the columns with the row factors.
+hipError_t a4_trial_direct(const A4Args &a, hipStream_t s);
+hipError_t a4_commit_direct(const A4Args &a, hipStream_t s);
 
 // The incremental peak search: rescan the stale tiles, then reduce the tile
 // keys into the peak key; and every tile stale.

@@ -69,12 +69,17 @@ struct asp_ctx {
     bool rf_ready = false;
     asp::RefreshArgs rf{};
     // the Asp-Clean2004 iteration: four padded grids and spectra, partial
-    // sums, the LM state and its pinned mirror, batched plans (first use)
+    // sums, the LM state and its pinned mirror, the batched inverse plan
+    // (first use)
     double *a4_grid = nullptr, *a4_part = nullptr;
     double2 *a4_spec = nullptr;
     asp::A4State *a4_state = nullptr, *a4_host = nullptr;
-    hipfftHandle a4_fwd = 0, a4_inv = 0;
+    hipfftHandle a4_inv = 0;
     bool a4_ready = false;
+    double *a4_taps = nullptr;            // per-axis factors of the rendering
+    double2 *a4_fac = nullptr;            // their 1-D DFTs
+    int32_t *a4_tapi = nullptr;
+    int32_t a4_conv = 0;                  // 0 cheaper of direct / FFT, 1 FFT, 2 direct
     asp::A4Args a4{};
     float *model_dev = nullptr;           // asp_model_image's device copy (first use)
     bool in_batch = false;                // a field of an asp_batch
@@ -128,10 +133,10 @@ void release(asp_ctx *c)
     if (c->rf_inv) (void)hipfftDestroy(c->rf_inv);
     (void)hipFree(c->dirty0); (void)hipFree(c->rf_grid); (void)hipFree(c->rf_spec);
     (void)hipFree(c->rf_pspec);
-    if (c->a4_fwd) (void)hipfftDestroy(c->a4_fwd);
     if (c->a4_inv) (void)hipfftDestroy(c->a4_inv);
     (void)hipFree(c->a4_grid); (void)hipFree(c->a4_part); (void)hipFree(c->a4_spec);
     (void)hipFree(c->a4_state);
+    (void)hipFree(c->a4_taps); (void)hipFree(c->a4_tapi); (void)hipFree(c->a4_fac);
     if (c->a4_host) (void)hipHostFree(c->a4_host);
     (void)hipFree(c->model_dev);
     if (c->st_host) (void)hipHostFree(c->st_host);
@@ -633,8 +638,9 @@ asp_status enqueue_iteration(asp_ctx *c)
 }
 
 
-// Buffers and batched plans of the Asp-Clean2004 iteration (first use); the
-// PSF's spectrum, its peak pixel and the single plans are the refresh's.
+// Buffers and the batched inverse plan of the Asp-Clean2004 iteration (first
+// use); the PSF's spectrum, its peak pixel and the single inverse plan are the
+// refresh's.
 asp_status setup_2004(asp_ctx *c)
 {
     if (c->a4_ready) return ASP_OK;
@@ -652,17 +658,17 @@ asp_status setup_2004(asp_ctx *c)
         e = dev_alloc(&c->a4_part, (size_t)asp::kA4Blocks * asp::kA4Sums);
     if (e == hipSuccess && !c->a4_state) e = dev_alloc(&c->a4_state, 1);
     if (e == hipSuccess && !c->a4_host) e = hipHostMalloc((void **)&c->a4_host, sizeof(asp::A4State));
+    if (e == hipSuccess && !c->a4_taps) e = dev_alloc(&c->a4_taps, (size_t)(3 * (c->H + c->W)));
+    if (e == hipSuccess && !c->a4_tapi) e = dev_alloc(&c->a4_tapi, 4);
+    if (e == hipSuccess && !c->a4_fac) e = dev_alloc(&c->a4_fac, (size_t)(3 * (Py + Px / 2 + 1)));
     if (e != hipSuccess)
         return fail(c, e == hipErrorOutOfMemory ? ASP_ERR_NOMEM : ASP_ERR_DEVICE,
                     std::string("Asp-Clean2004 buffers: ") + hipGetErrorString(e));
     HIP_OR_FAIL(c, hipMemsetAsync(c->a4_state, 0, sizeof(asp::A4State), c->stream));
     int n[2] = {(int)Py, (int)Px};
     hipfftResult fr = HIPFFT_SUCCESS;
-    if (!c->a4_fwd)
-        fr = hipfftPlanMany(&c->a4_fwd, 2, n, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_D2Z, 4);
-    if (fr == HIPFFT_SUCCESS && !c->a4_inv)
+    if (!c->a4_inv)
         fr = hipfftPlanMany(&c->a4_inv, 2, n, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, 4);
-    if (fr == HIPFFT_SUCCESS) fr = hipfftSetStream(c->a4_fwd, c->stream);
     if (fr == HIPFFT_SUCCESS) fr = hipfftSetStream(c->a4_inv, c->stream);
     if (fr != HIPFFT_SUCCESS)
         return fail(c, ASP_ERR_DEVICE, std::string("Asp-Clean2004 plans: ") + fft_text(fr));
@@ -677,6 +683,12 @@ asp_status setup_2004(asp_ctx *c)
     a.spec = c->a4_spec;
     a.pspec = r.pspec;
     a.partials = c->a4_part;
+    a.psf = c->psf;
+    a.taps = c->a4_taps;
+    a.fac = c->a4_fac;
+    a.tapi = c->a4_tapi;
+    a.grid_cap = 4 * (int64_t)plane;
+    a.Hp = c->Hp; a.Wp = c->Wp;
     a.H = c->H; a.W = c->W; a.Py = Py; a.Px = Px;
     a.ci = r.ci; a.cj = r.cj;
     a.budget = c->opt.lm_max_iter;
@@ -691,6 +703,43 @@ asp_status setup_2004(asp_ctx *c)
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     c->a4_ready = true;
     return ASP_OK;
+}
+
+// The direct convolution's multiply-add slots that take about as long as the
+// FFT route per padded pixel: an evaluation (factor DFTs, spectral product,
+// batched inverse transform, sums) and the update (one inverse transform).
+constexpr double kA4FftEval = 1000.0, kA4FftUpdate = 250.0;
+
+// Taps per axis of the rendering at squared width v: 12 for the narrow
+// rendering, 2 h + 1 for the sampled Gaussian (at least 12 either way, so the
+// count grows with v), clipped to the image by the caller.
+int64_t a4_taps_bound(const asp_ctx *c, double v)
+{
+    const double om = sqrt(v > 0.0 ? v : 0.0);
+    const int64_t n = om >= 1.0 ? 2 * (int64_t)asp::halfwidth(om, c->opt.window_sigmas) + 1 : 12;
+    return n < 12 ? 12 : n;
+}
+
+// Whether an Asp-Clean2004 evaluation (planes 3) or update (planes 1)
+// convolves directly.  v_cap bounds the squared width of every point the
+// launches may meet: at that width the row pass's (H + nr - 1) x W rows per
+// factor must fit the grids.  v is the width of the point itself: by default
+// the direct route's multiply-add slots, planes nc (H + nr - 1) W for the row
+// pass and (5 or 1) (nr + 3) H W for the column pass, must undercut
+// kA4FftEval (kA4FftUpdate) per padded pixel.
+bool a4_direct(const asp_ctx *c, double v, double v_cap, int planes)
+{
+    if (c->a4_conv == 1) return false;
+    const double H = (double)c->H, W = (double)c->W;
+    const double padded = (double)c->rf.Py * (double)c->rf.Px;
+    const double ncap = (double)std::min(a4_taps_bound(c, v_cap), c->H);
+    if ((double)planes * (H + ncap - 1.0) * W > 4.0 * padded) return false;
+    if (c->a4_conv == 2) return true;
+    const double nr = (double)std::min(a4_taps_bound(c, v), c->H);
+    const double nc = (double)std::min(a4_taps_bound(c, v), c->W);
+    const double slots = (double)planes * nc * (H + nr - 1.0) * W +
+                         (planes == 3 ? 5.0 : 1.0) * (nr + 3.0) * H * W;
+    return slots <= (planes == 3 ? kA4FftEval : kA4FftUpdate) * padded;
 }
 
 asp_status pull_a4(asp_ctx *c)
@@ -731,19 +780,33 @@ asp_status step_2004(asp_ctx *c, asp_fit2004_report *rep)
     // at most budget + 1 are needed.  On small grids, where an evaluation
     // costs less than the host's round trip, four are queued between reads of
     // the LM state; those queued after the end return at once (their FFTs
-    // transform the stale grids, which the update clears).
+    // inverse-transform stale spectra).  The convolution is chosen per read,
+    // by the squared width of the next point; when four are queued, the fit
+    // bound on that width must also let the direct route fit the grids.
     const int per_read = c->rf.Py * c->rf.Px <= (int64_t)1024 * 1024 ? 4 : 1;
+    int32_t direct_evals = 0;
     for (int32_t queued = 0; !c->a4_host->done;) {
         if (queued >= c->a4.budget + 1)
             return fail(c, ASP_ERR_STATE, "the Asp-Clean2004 fit did not end within its budget");
+        const bool direct = a4_direct(c, c->a4_host->te[3],
+                                      per_read == 1 ? c->a4_host->te[3] : c->a4_host->hi[3], 3);
+        const int32_t evals0 = c->a4_host->evals;
         for (int b = 0; b < per_read && queued < c->a4.budget + 1; ++b, ++queued) {
-            s = timed(c, 7, [&] { return asp::a4_trial(c->a4, &c->a4_fwd, &c->a4_inv, c->stream); });
+            s = timed(c, 7, [&] {
+                return direct ? asp::a4_trial_direct(c->a4, c->stream)
+                              : asp::a4_trial(c->a4, &c->a4_inv, c->stream);
+            });
             if (s != ASP_OK) return s;
         }
         s = pull_a4(c);
         if (s != ASP_OK) return s;
+        if (direct) direct_evals += c->a4_host->evals - evals0;
     }
-    s = timed(c, 8, [&] { return asp::a4_commit(c->a4, &c->rf_fwd, &c->rf_inv, c->stream); });
+    const bool direct_up = a4_direct(c, c->a4_host->theta[3], c->a4_host->theta[3], 1);
+    s = timed(c, 8, [&] {
+        return direct_up ? asp::a4_commit_direct(c->a4, c->stream)
+                         : asp::a4_commit(c->a4, &c->rf_inv, c->stream);
+    });
     if (s != ASP_OK) return s;
     if (c->pk_tiles) HIP_OR_FAIL(c, asp::launch_peak_mark_all(c->P, c->stream));
     HIP_OR_FAIL(c, asp::launch_smooth_mark_all(c->P, c->stream));
@@ -759,6 +822,8 @@ asp_status step_2004(asp_ctx *c, asp_fit2004_report *rep)
         rep->trials = a->trials;
         rep->converged = a->converged;
         rep->evaluations = a->evals;
+        rep->direct_evals = direct_evals;
+        rep->direct_update = direct_up ? 1 : 0;
         for (int i = 0; i < 4; ++i) {
             rep->start[i] = h->smooth_start[i];
             rep->theta0[i] = a->theta0[i];
@@ -1335,6 +1400,13 @@ asp_status asp_step_2004(asp_ctx *c, asp_fit2004_report *rep)
     if (c->in_batch)
         return fail(c, ASP_ERR_STATE, "the Asp-Clean2004 iteration is not available to batched fields");
     return step_2004(c, rep);
+}
+
+asp_status asp_set_2004_convolution(asp_ctx *c, int32_t mode)
+{
+    if (!c || mode < 0 || mode > 2) return ASP_ERR_INVALID_ARG;
+    c->a4_conv = mode;
+    return ASP_OK;
 }
 
 asp_status asp_run_2004(asp_ctx *c, int64_t n_iter, asp_run_report *rep)

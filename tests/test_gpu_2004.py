@@ -1,6 +1,6 @@
 """The Asp-Clean2004 iteration on the GPU (asp_step_2004 / asp_run_2004: the
-objective of Eq. 3 with the true PSF convolved by FFT in every evaluation)
-against the FP64 oracle (oracle/asp2004.py).
+objective of Eq. 3 with the true PSF convolved in every evaluation, by FFT or
+directly as two 1-D passes) against the FP64 oracle (oracle/asp2004.py).
 
 Lockstep: before every GPU step the oracle is loaded with the GPU's residual
 and component list and takes the same step.  Compared: the peak, the
@@ -48,9 +48,10 @@ def errors(g, o, wb):
                      abs(g[3] - o[3]) / (PARAM_RTOL * s2)])
 
 
-def lockstep(f, steps, gain=None, need_strict=1, **kw):
+def lockstep(f, steps, gain=None, need_strict=1, mode="auto", **kw):
     gain = f.gain if gain is None else gain
     ctx = asp.Context(f.dirty, f.psf, gain, f.threshold, max_iter=f.max_iter, **kw)
+    ctx.set_2004_convolution(mode)
     gain = float(np.float32(gain))            # the loop gain crosses the C ABI as FP32
     ab, wb = ctx.psf_gauss()
     D = f.dirty.astype(np.float64)
@@ -63,6 +64,10 @@ def lockstep(f, steps, gain=None, need_strict=1, **kw):
         rc, rep = ctx.step_2004()
         if rc in (asp.ASP_STOP_THRESHOLD, asp.ASP_STOP_MAXITER):
             break
+        if mode == "fft":
+            assert rep["direct_evals"] == 0 and rep["direct_update"] == 0
+        elif mode == "direct":
+            assert rep["direct_evals"] == rep["evaluations"] and rep["direct_update"] == 1
         R0d = R0.astype(np.float64)
         exact = smoothing_start_ok(rep["start"], rep["scale"], R0d, wb, orc.s_max)
         orc.load_state(R0, comps0, k0)
@@ -94,13 +99,18 @@ def lockstep(f, steps, gain=None, need_strict=1, **kw):
     return ctx, regimes
 
 
-def test_lockstep_evla128():
+CONVS = ["fft", "direct"]
+
+
+@pytest.mark.parametrize("conv", CONVS)
+def test_lockstep_evla128(conv):
     f = skygen.make_evla(128, 7, 40, 4, 10.0, 200, 1, psf_crop=128)
-    ctx, regimes = lockstep(f, 8, gain=0.3, need_strict=5)
+    ctx, regimes = lockstep(f, 8, gain=0.3, need_strict=5, mode=conv)
     ctx.close()
 
 
-def test_lockstep_ragged_asymmetric_psf():
+@pytest.mark.parametrize("conv", CONVS)
+def test_lockstep_ragged_asymmetric_psf(conv):
     """A ragged image and an odd, off-centre PSF with a sidelobe: a point
     between pixels and a wide Gaussian."""
     rng = np.random.default_rng(11)
@@ -122,7 +132,7 @@ def test_lockstep_ragged_asymmetric_psf():
     dirty += rng.normal(0.0, 1e-3, size=(H, W))
     g = skygen.Field("ragged", dirty.astype(np.float32), psf.astype(np.float32), 0.5, 0.0, 20, 1,
                      np.zeros((0, 3)), np.zeros((0, 4)), 1e-3)
-    ctx, regimes = lockstep(g, 6, need_strict=3)
+    ctx, regimes = lockstep(g, 6, need_strict=3, mode=conv)
     ctx.close()
 
 
@@ -188,12 +198,14 @@ def test_mixed_with_the_2016_iteration():
     ctx.close()
 
 
-def test_c4096_two_iterations():
+@pytest.mark.parametrize("mode", ["auto", "fft"])
+def test_c4096_two_iterations(mode):
     """The 4096 x 4096 field: two iterations; each update against the oracle's
     FFT convolution at the GPU's parameters, at sampled pixels and in RMS."""
     f = skygen.make_c4096(4096)
-    print("c4096 2004", flush=True)
+    print("c4096 2004", mode, flush=True)
     ctx = asp.Context(f.dirty, f.psf, f.gain, f.threshold, max_iter=f.max_iter)
+    ctx.set_2004_convolution(mode)
     ab, wb = ctx.psf_gauss()
     D = f.dirty.astype(np.float64)
     rng = np.random.default_rng(7)
@@ -202,7 +214,10 @@ def test_c4096_two_iterations():
         R0 = ctx.residual().astype(np.float64)
         rc, rep = ctx.step_2004()
         assert rc in (asp.ASP_OK, asp.ASP_LM_NOT_CONVERGED)
-        print("  theta", rep["theta"], "trials", rep["trials"], flush=True)
+        print("  theta", rep["theta"], "trials", rep["trials"], "direct", rep["direct_evals"],
+              "of", rep["evaluations"], "update", rep["direct_update"], flush=True)
+        if mode == "fft":
+            assert rep["direct_evals"] == 0 and rep["direct_update"] == 0
         th = rep["theta"]
         g32 = float(np.float32(f.gain))
         conv = a4.Problem(R0, f.psf, wb).convolved([g32 * th[0], th[1], th[2], th[3]])
@@ -234,13 +249,16 @@ def test_edge_cases():
     for shape in [(1, 1), (3, 5), (7, 1)]:
         dirty = np.zeros(shape, np.float32)
         dirty[shape[0] // 2, shape[1] // 2] = 1.0
-        print("shape", shape, flush=True)
-        ctx = asp.Context(dirty, psf, 0.3, 0.0, max_iter=5)
-        R0 = ctx.residual().astype(np.float64)
-        rc, rep = ctx.step_2004()
-        assert rc in (asp.ASP_OK, asp.ASP_LM_NOT_CONVERGED), shape
-        assert update_ok(ctx, R0, psf, g03, rep["theta"], dirty), shape
-        ctx.close()
+        for conv in CONVS:
+            print("shape", shape, conv, flush=True)
+            ctx = asp.Context(dirty, psf, 0.3, 0.0, max_iter=5)
+            ctx.set_2004_convolution(conv)
+            R0 = ctx.residual().astype(np.float64)
+            rc, rep = ctx.step_2004()
+            assert rc in (asp.ASP_OK, asp.ASP_LM_NOT_CONVERGED), shape
+            assert rep["direct_update"] == (conv == "direct"), shape
+            assert update_ok(ctx, R0, psf, g03, rep["theta"], dirty), shape
+            ctx.close()
     f = skygen.make_evla(128, 7, 40, 4, 10.0, 200, 1, psf_crop=128)
     g = float(np.float32(f.gain))
     ctx = asp.Context(f.dirty, f.psf, f.gain, 0.0, max_iter=5, lm_max_iter=1, smooth_norm=1)
@@ -265,6 +283,15 @@ def test_edge_cases():
     ctx.step_2004()
     with pytest.raises(asp.AspError):
         ctx.step_2004()
+    ctx.close()
+
+
+def test_convolution_mode_is_checked():
+    f = skygen.make_evla(128, 7, 40, 4, 10.0, 200, 1, psf_crop=128)
+    ctx = asp.Context(f.dirty, f.psf, f.gain, 0.0, max_iter=5)
+    for bad in (-1, 3):
+        with pytest.raises(asp.AspError):
+            ctx.set_2004_convolution(bad)
     ctx.close()
 
 
