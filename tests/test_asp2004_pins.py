@@ -4,7 +4,10 @@ evaluation.  The checks come from outside the oracle: central finite
 differences of the rendered images, the closed form of a Gaussian sky
 component convolved with a Gaussian PSF (alone and with an offset sidelobe,
 which fixes the orientation of the convolution), the shifted PSF of a point
-between pixels, and the exact-PSF refresh oracle for the residual update."""
+between pixels, and the exact-PSF refresh oracle for the residual update.  The
+rendered images are also checked to be sums of outer products of per-axis
+factors, the structure both GPU convolutions (separable spectra and the
+two-pass direct sum) are built on."""
 import math
 
 import numpy as np
@@ -56,6 +59,31 @@ def test_derivatives_against_finite_differences(x, y, v):
         gm = a4.unit_images(shape, x - e[0], y - e[1], v - e[2])[0]
         fd = (gp - gm) / (2 * h)
         assert np.abs(fd - d).max() <= 1e-6 * max(1.0, np.abs(d).max()), k
+
+
+def _rank(m, rel=1e-12):
+    sv = np.linalg.svd(m, compute_uv=False)
+    return int(np.sum(sv > rel * sv[0])) if sv[0] > 0 else 0
+
+
+@pytest.mark.parametrize("x,y,v", [(10.3, 12.7, 2.3 ** 2), (15.37, 14.81, 0.45 ** 2),
+                                   (9.62, 20.18, 0.0), (1.2, 30.6, 3.1 ** 2),
+                                   (0.4, 0.3, 0.2 ** 2), (34.8, 2.2, 6.5 ** 2)])
+def test_rendering_is_a_sum_of_outer_products(x, y, v):
+    """The structure the GPU's convolutions rely on: g = a0 b0^T, dg/dx = a0 b1^T,
+    dg/dy = a1 b0^T and dg/dv = a2 b0^T + a0 b2^T, for sampled and interpolated
+    components, clipped at the image's edges or not.  Checked by ranks: g, dg/dx
+    and dg/dy have rank 1; g beside dg/dx (the same row factor) and g above
+    dg/dy (the same column factor) too; dg/dv has rank 2 and shares a0 and b0."""
+    shape = (32, 36)
+    g, gx, gy, gv = a4.unit_images(shape, x, y, v)
+    assert _rank(g) == 1 and _rank(gx) == 1 and _rank(gy) == 1
+    assert _rank(np.hstack([g, gx])) == 1 and _rank(np.vstack([g, gy])) == 1
+    assert _rank(gv) <= 2
+    assert _rank(np.hstack([g, gv])) <= 2 and _rank(np.vstack([g, gv])) <= 2
+    # and not trivially: a non-separable image fails the same test
+    q = g + np.roll(g, 3, axis=0) * np.roll(g, 2, axis=1) / max(g.max(), 1e-300)
+    assert _rank(q) > 1
 
 
 def test_unit_flux():
