@@ -474,8 +474,10 @@ asp_status asp_refresh_residual(asp_ctx *ctx);
  *      asp_refresh_residual read it like any other.
  * Earlier components are not refitted.  The host reads the device's LM state
  * after each evaluation (after every four on padded grids of at most 1024^2
- * pixels, where evaluations queued past the end of the fit return at once).  The first call allocates four FP64 grids and their
- * spectra of the refresh's padded size and batched FFT plans.  Must not be
+ * pixels, where evaluations queued past the end of the fit return at once).
+ * The first call allocates four FP64 grids and their spectra of the
+ * refresh's padded size, the per-axis factors of the rendering and their 1-D
+ * DFTs, and a batched inverse FFT plan.  Must not be
  * inside a find_peak / fit / update sequence (ASP_ERR_STATE); not available
  * to batched fields.  Returns ASP_OK, ASP_LM_NOT_CONVERGED (budget used),
  * ASP_STOP_THRESHOLD or ASP_STOP_MAXITER.  rep may be NULL.
