@@ -136,6 +136,15 @@ def test_lockstep_ragged_asymmetric_psf(conv):
     ctx.close()
 
 
+def test_lockstep_direct_1024():
+    """The direct route where the column pass takes 16-row tiles (images whose
+    tiles of that height fill its grid) and the row pass several 256-column
+    blocks: a 1024^2 EVLA-like field, every evaluation and update direct."""
+    f = skygen.make_evla(1024, 13, 120, 6, 12.0, 50, 1, psf_crop=256)
+    ctx, regimes = lockstep(f, 3, gain=0.3, need_strict=1, mode="direct")
+    ctx.close()
+
+
 def test_run_matches_steps_and_refresh_agrees():
     """asp_run_2004 gives the step API's state bit for bit; afterwards the
     exact-PSF refresh of the list reproduces the residual to the FP32 roundings
